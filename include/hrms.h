@@ -1,0 +1,196 @@
+/*
+ * hrms.h -- C ABI of the MI355X (gfx950) incoherent harmonic-sum library.
+ *
+ * Implements the harmonic sums of K. Adamek and W. Armour, "A GPU
+ * implementation of the harmonic sum algorithm" (arXiv:1812.02647):
+ *
+ *   HRMS_EQ1      eq. (1), Sec. 1  h(n)_H = H^-1/2 sum_{i=1..H} x(round(n i / H))
+ *   HRMS_MAX      eq. (2), Sec. 2  h(n)_H = H^-1/2 sum_{i=1..H} max_{0<=j<i} x(i n + j)
+ *   HRMS_FREQBIN  eq. (3), Sec. 2  h(n)_H = H^-1/2 sum_{i=1..H} x(i n)
+ *   HRMS_GREEDY   eq. (4), Sec. 2  start at x(n), j = 0; harmonic k = 2..H adds
+ *                                  the larger of x(k n + j), x(k n + j + 1) and
+ *                                  moves j up by one when the right bin is
+ *                                  strictly larger
+ *
+ * over batches of 1D power spectra (the periodicity search after the FFT,
+ * Sec. 1) and, for FREQBIN and GREEDY, over a 2D frequency x fdot plane (the
+ * sum that follows the Fourier-domain acceleration search; abstract, Sec. 1).
+ *
+ * Conventions shared by every entry point
+ *   - Levels are H = 1, 2, 4, ..., hmax with hmax a power of two <= 32
+ *     ("partial sums of an increasing number of harmonics", Sec. 1).
+ *   - round() in eq. (1) rounds halves up; the fdot row of the 2D sum rounds
+ *     halves away from zero. All index arithmetic is exact integer arithmetic.
+ *   - Level H of output n exists for every n with eq. (1), and for
+ *     n < floor(N / H) with eq. (2)-(4) (their last index H n + H - 1 must lie in
+ *     the spectrum). Outputs are "compact": the level-H plane of eq. (2)-(4)
+ *     holds floor(N / H) values, that of eq. (1) holds N values.
+ *   - Sums are accumulated in FP32, harmonics added in the order i = 1..H of
+ *     the equations, each level of eq. (1) summed on its own; h = S * r_H with
+ *     r_H the FP32 value of 1/sqrt(H). No multiply-add contraction is used.
+ *   - SNR (reported by the paper, Sec. 3, without a definition) is the
+ *     standardisation snr_H = (h_H - m_H) * q_H with m_H, 1/q_H the null mean
+ *     and standard deviation of h_H for independent bins of mean mu and
+ *     standard deviation sigma (exact for exponential, i.e. chi-square 2 dof,
+ *     noise; constants evaluated in FP64 and rounded once to FP32).
+ *     max_snr[n] is the largest snr over the existing levels of n; best_h[n] is
+ *     the H that attains it (the smallest such H on ties).
+ *   - mu and sigma are the population mean and standard deviation of all bins
+ *     of a spectrum (or plane), reduced in FP64 on the device, or supplied by
+ *     the caller.
+ *
+ * Memory and threads
+ *   - Buffers marked "device" are device pointers allocated by the caller
+ *     (hipMalloc, or torch tensors on a HIP device). The library never frees
+ *     caller memory. "host" arrays are read during the call only.
+ *   - Work is enqueued asynchronously on the given HIP stream (NULL = the null
+ *     stream). Buffers must stay alive until the stream reaches the work.
+ *   - A handle is not thread-safe; use one handle per host thread.
+ *   - Every argument is checked before anything is enqueued. On error nothing
+ *     is enqueued, no output is touched and a negative status is returned;
+ *     hrms_last_error() gives the reason. No call aborts or throws.
+ */
+#ifndef HRMS_H
+#define HRMS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hrms_ctx* hrms_handle;
+
+enum { HRMS_EQ1 = 0, HRMS_MAX = 1, HRMS_FREQBIN = 2, HRMS_GREEDY = 3 };
+
+/* Storage type of the input bins. FP16 and BF16 widen exactly to FP32 before
+ * any arithmetic. */
+enum { HRMS_F32 = 0, HRMS_F16 = 1, HRMS_BF16 = 2 };
+
+/* Output selection bits. */
+enum { HRMS_OUT_H = 1u, HRMS_OUT_MAXSNR = 2u, HRMS_OUT_BESTH = 4u };
+
+enum { HRMS_STATS_COMPUTE = 0, HRMS_STATS_PROVIDED = 1 };
+
+enum {
+    HRMS_OK = 0,
+    HRMS_E_INVAL = -1,       /* an argument is invalid (see hrms_last_error) */
+    HRMS_E_UNSUPPORTED = -2, /* valid request this build does not implement */
+    HRMS_E_NODEVICE = -3,    /* no usable gfx950 device */
+    HRMS_E_NOMEM = -4,       /* device or host allocation failed */
+    HRMS_E_HIP = -5          /* a HIP runtime call failed */
+};
+
+#define HRMS_MAX_HMAX 32
+#define HRMS_MAX_LEVELS 6
+/* Largest spectrum (or plane row) length: keeps every index H*n + H below 2^31. */
+#define HRMS_MAX_BINS (1 << 26)
+
+/* A batch of 1D power spectra (DM trials), packed back to back. */
+typedef struct {
+    int32_t n_spectra;        /* >= 1 */
+    int32_t variant;          /* HRMS_EQ1 .. HRMS_GREEDY */
+    int32_t dtype;            /* HRMS_F32 / HRMS_F16 / HRMS_BF16 */
+    int32_t hmax_all;         /* Hmax of every spectrum when hmax == NULL */
+    uint32_t out_mask;        /* HRMS_OUT_* bits; 0 computes only the statistics */
+    int32_t stats_mode;       /* HRMS_STATS_COMPUTE or HRMS_STATS_PROVIDED */
+    const void* x;            /* device: offsets[n_spectra] bins of `dtype`; the
+                                 bins of spectrum s are x[offsets[s] .. offsets[s+1]) */
+    const int64_t* offsets;   /* host: n_spectra + 1 values, offsets[0] = 0,
+                                 each spectrum 1 .. HRMS_MAX_BINS bins long */
+    const uint8_t* hmax;      /* host: per-spectrum Hmax, or NULL for hmax_all */
+    double* stats;            /* device: [n_spectra][2] = (mu, sigma); written
+                                 (COMPUTE) or read (PROVIDED) */
+    float* snr_consts;        /* device or NULL: [n_spectra][HRMS_MAX_LEVELS][2]
+                                 = (m_H, q_H) of the run's variant, written;
+                                 unused levels are written as 0 */
+    float* h;                 /* device: compact level planes at the offsets
+                                 given by hrms_layout_1d; needed iff OUT_H */
+    float* max_snr;           /* device: offsets[n_spectra] floats; iff OUT_MAXSNR */
+    uint8_t* best_h;          /* device: offsets[n_spectra] bytes (the H value);
+                                 iff OUT_BESTH */
+} hrms_run1d_args;
+
+/* One frequency x fdot plane: row r = z + zmax holds fdot z, z = -zmax..zmax.
+ * Output (m, z) of level H is the fundamental at frequency bin m whose H-th
+ * harmonic has fdot z; harmonic i is read at frequency i*m (FREQBIN) or
+ * i*m + j (GREEDY, j as in eq. (4)) from row round(i z / H) + zmax. Output
+ * (m, z) of level H exists for m < floor(nf / H). */
+typedef struct {
+    int32_t nf;               /* frequency bins per row, 1 .. HRMS_MAX_BINS */
+    int32_t zmax;             /* >= 0 */
+    int32_t hmax;             /* power of two <= 32 */
+    int32_t variant;          /* HRMS_FREQBIN or HRMS_GREEDY (others: HRMS_E_UNSUPPORTED) */
+    int32_t dtype;
+    uint32_t out_mask;
+    int32_t stats_mode;
+    int32_t reserved;         /* must be 0 */
+    int64_t ld;               /* row stride in bins, >= nf */
+    const void* x;            /* device: (2 zmax + 1) rows of ld bins */
+    double* stats;            /* device: [2] = (mu, sigma) over the nf bins of every row */
+    float* snr_consts;        /* device or NULL: [HRMS_MAX_LEVELS][2] */
+    float* h;                 /* device: level H plane [2 zmax + 1][floor(nf / H)],
+                                 packed level after level (hrms_layout_2d) */
+    float* max_snr;           /* device: [2 zmax + 1][nf] */
+    uint8_t* best_h;          /* device: [2 zmax + 1][nf] */
+} hrms_run2d_args;
+
+/* Normalisation to unit mean and narrow storage (FP16 / BF16) of FP32 spectra:
+ * y = round_to_dtype(x * fl32(1/mu)), rounding to nearest even, FP16 saturating
+ * at +-65504. The statistics of y are taken as mu' = 1, sigma' = sigma / mu. */
+typedef struct {
+    int32_t n_spectra;
+    int32_t dtype;            /* HRMS_F16 or HRMS_BF16 */
+    int32_t stats_mode;       /* COMPUTE: raw (mu, sigma) are reduced into stats;
+                                 PROVIDED: they are read from stats */
+    int32_t reserved;         /* must be 0 */
+    const float* x;           /* device, FP32, packed as in hrms_run1d_args */
+    const int64_t* offsets;   /* host */
+    double* stats;            /* device [n_spectra][2]: raw (mu, sigma) */
+    double* stats_out;        /* device [n_spectra][2]: (1, sigma / mu) of y */
+    void* y;                  /* device: offsets[n_spectra] 2-byte bins */
+} hrms_quantize_args;
+
+/* Creates a handle bound to HIP device `device_ordinal` (made current for
+ * every later call on the handle). tune_cache_path: file holding tuned launch
+ * shapes, or NULL. Returns HRMS_E_NODEVICE when the device is absent or not
+ * gfx950. *out is set only on success. */
+int hrms_create(hrms_handle* out, int device_ordinal, const char* tune_cache_path);
+
+/* Releases the handle's workspace, plans and graphs. Accepts NULL. */
+int hrms_destroy(hrms_handle h);
+
+/* Host-only: layout of the compact h planes of a 1D batch. plane_offsets (host,
+ * may be NULL) receives [n_spectra][HRMS_MAX_LEVELS] float offsets into h
+ * (-1 for levels above the spectrum's Hmax); *h_total_floats (may be NULL) the
+ * number of floats h must hold. Validates `a` exactly as hrms_run_1d does,
+ * except for device pointers. Needs no device. */
+int hrms_layout_1d(const hrms_run1d_args* a, int64_t* plane_offsets, int64_t* h_total_floats);
+
+/* Host-only: same for a 2D plane; plane_offsets has HRMS_MAX_LEVELS entries. */
+int hrms_layout_2d(const hrms_run2d_args* a, int64_t* plane_offsets, int64_t* h_total_floats);
+
+/* Harmonic sum of a 1D batch: statistics (unless provided), SNR constants,
+ * then every level of every spectrum in one persistent launch. `hip_stream` is
+ * a hipStream_t or NULL. */
+int hrms_run_1d(hrms_handle h, const hrms_run1d_args* a, void* hip_stream);
+
+/* Harmonic sum of a 2D plane (FREQBIN and GREEDY). */
+int hrms_run_2d(hrms_handle h, const hrms_run2d_args* a, void* hip_stream);
+
+/* Normalise and store FP32 spectra as FP16 / BF16 (precision form of the 1D
+ * batch and of a plane with ld == nf, passed as one spectrum). */
+int hrms_quantize(hrms_handle h, const hrms_quantize_args* a, void* hip_stream);
+
+/* Static description of a status code. */
+const char* hrms_strerror(int status);
+
+/* Detail of the last error on this handle (empty string if none; a static
+ * string for NULL handles). Valid until the next call on the handle. */
+const char* hrms_last_error(hrms_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HRMS_H */

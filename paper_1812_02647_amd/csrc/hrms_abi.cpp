@@ -1,0 +1,538 @@
+// hrms_abi.cpp -- host runtime behind the C ABI declared in include/hrms.h.
+//
+// Validation and layout are plain host code (usable with no device present).
+// The runtime turns a batch into a plan -- per-spectrum descriptors, a
+// cost-sorted tile list for the persistent harmonic-sum launch, statistics
+// segments and a constants table -- caches it by batch signature, and enqueues
+// statistics -> constants -> harmonic sum on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/hrms.h"
+#include "hrms_internal.h"
+
+using namespace hrms;
+
+namespace {
+
+constexpr int kStatsSeg = 1 << 16;   // bins per statistics segment
+constexpr int kPlanCache = 4;
+
+thread_local std::string g_last_error;
+
+struct DeviceBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    ~DeviceBuf() { release(); }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    hipError_t ensure(size_t n)
+    {
+        if (n <= bytes && p) return hipSuccess;
+        release();
+        if (n == 0) n = 16;
+        hipError_t e = hipMalloc(&p, n);
+        if (e != hipSuccess) {
+            p = nullptr;
+            return e;
+        }
+        bytes = n;
+        return hipSuccess;
+    }
+};
+
+struct Plan1D {
+    // signature
+    std::vector<int64_t> offsets;
+    std::vector<uint8_t> nlev;
+    int variant = 0, dtype = 0;
+    Shape1D shape{};
+    // host mirrors (kept alive for the asynchronous uploads)
+    std::vector<SpecDesc> spec;
+    std::vector<Tile> tiles;
+    std::vector<Seg> segs;
+    std::vector<int32_t> seg_first;
+    int grid = 0;
+    // device
+    DeviceBuf d_spec, d_tiles, d_segs, d_seg_first, d_partial, d_consts, d_counter;
+    bool uploaded = false;
+};
+
+}  // namespace
+
+struct hrms_ctx {
+    int device = 0;
+    int cu_count = 0;
+    std::string err;
+    std::string tune_path;
+    std::vector<std::unique_ptr<Plan1D>> plans;   // most recent last
+};
+
+namespace {
+
+int fail(hrms_ctx* c, int status, const std::string& msg)
+{
+    if (c)
+        c->err = msg;
+    else
+        g_last_error = msg;
+    return status;
+}
+
+int hip_fail(hrms_ctx* c, hipError_t e, const char* what)
+{
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    return fail(c, e == hipErrorOutOfMemory ? HRMS_E_NOMEM : HRMS_E_HIP, m);
+}
+
+int levels_of_hmax(int h)
+{
+    if (h < 1 || h > HRMS_MAX_HMAX || (h & (h - 1))) return -1;
+    int l = 0;
+    while ((1 << l) < h) ++l;
+    return l + 1;
+}
+
+int dtype_bytes(int dt) { return dt == HRMS_F32 ? 4 : 2; }
+
+// ---------------------------------------------------------------------------
+// Validation (host only)
+// ---------------------------------------------------------------------------
+
+int validate_1d(hrms_ctx* c, const hrms_run1d_args* a, bool device_ptrs)
+{
+    if (!a) return fail(c, HRMS_E_INVAL, "args is NULL");
+    if (a->n_spectra < 1) return fail(c, HRMS_E_INVAL, "n_spectra must be >= 1");
+    if (a->variant < HRMS_EQ1 || a->variant > HRMS_GREEDY)
+        return fail(c, HRMS_E_INVAL, "variant must be HRMS_EQ1..HRMS_GREEDY");
+    if (a->dtype < HRMS_F32 || a->dtype > HRMS_BF16)
+        return fail(c, HRMS_E_INVAL, "dtype must be HRMS_F32, HRMS_F16 or HRMS_BF16");
+    if (a->out_mask & ~7u) return fail(c, HRMS_E_INVAL, "out_mask has unknown bits");
+    if (a->stats_mode != HRMS_STATS_COMPUTE && a->stats_mode != HRMS_STATS_PROVIDED)
+        return fail(c, HRMS_E_INVAL, "stats_mode must be COMPUTE or PROVIDED");
+    if (!a->offsets) return fail(c, HRMS_E_INVAL, "offsets is NULL");
+    if (a->offsets[0] != 0) return fail(c, HRMS_E_INVAL, "offsets[0] must be 0");
+    for (int s = 0; s < a->n_spectra; ++s) {
+        const int64_t len = a->offsets[s + 1] - a->offsets[s];
+        if (len < 1 || len > HRMS_MAX_BINS)
+            return fail(c, HRMS_E_INVAL,
+                        "spectrum " + std::to_string(s) + " has " + std::to_string(len) +
+                            " bins (allowed 1.." + std::to_string(HRMS_MAX_BINS) + ")");
+        const int hm = a->hmax ? a->hmax[s] : a->hmax_all;
+        if (levels_of_hmax(hm) < 0)
+            return fail(c, HRMS_E_INVAL, "Hmax of spectrum " + std::to_string(s) + " is " +
+                                             std::to_string(hm) +
+                                             " (must be a power of two <= 32)");
+    }
+    if (device_ptrs) {
+        if (!a->x) return fail(c, HRMS_E_INVAL, "x is NULL");
+        if (reinterpret_cast<uintptr_t>(a->x) % 16)
+            return fail(c, HRMS_E_INVAL, "x must be 16-byte aligned");
+        if (!a->stats) return fail(c, HRMS_E_INVAL, "stats is NULL");
+        if ((a->out_mask & HRMS_OUT_H) && !a->h)
+            return fail(c, HRMS_E_INVAL, "h is NULL but HRMS_OUT_H is set");
+        if ((a->out_mask & HRMS_OUT_MAXSNR) && !a->max_snr)
+            return fail(c, HRMS_E_INVAL, "max_snr is NULL but HRMS_OUT_MAXSNR is set");
+        if ((a->out_mask & HRMS_OUT_BESTH) && !a->best_h)
+            return fail(c, HRMS_E_INVAL, "best_h is NULL but HRMS_OUT_BESTH is set");
+    }
+    return HRMS_OK;
+}
+
+int validate_2d(hrms_ctx* c, const hrms_run2d_args* a, bool device_ptrs)
+{
+    if (!a) return fail(c, HRMS_E_INVAL, "args is NULL");
+    if (a->nf < 1 || a->nf > HRMS_MAX_BINS)
+        return fail(c, HRMS_E_INVAL, "nf must be in 1.." + std::to_string(HRMS_MAX_BINS));
+    if (a->zmax < 0 || a->zmax > 4096) return fail(c, HRMS_E_INVAL, "zmax must be in 0..4096");
+    if (a->ld < a->nf) return fail(c, HRMS_E_INVAL, "ld must be >= nf");
+    if (levels_of_hmax(a->hmax) < 0)
+        return fail(c, HRMS_E_INVAL, "hmax must be a power of two <= 32");
+    if (a->variant < HRMS_EQ1 || a->variant > HRMS_GREEDY)
+        return fail(c, HRMS_E_INVAL, "variant must be HRMS_EQ1..HRMS_GREEDY");
+    if (a->dtype < HRMS_F32 || a->dtype > HRMS_BF16)
+        return fail(c, HRMS_E_INVAL, "dtype must be HRMS_F32, HRMS_F16 or HRMS_BF16");
+    if (a->out_mask & ~7u) return fail(c, HRMS_E_INVAL, "out_mask has unknown bits");
+    if (a->stats_mode != HRMS_STATS_COMPUTE && a->stats_mode != HRMS_STATS_PROVIDED)
+        return fail(c, HRMS_E_INVAL, "stats_mode must be COMPUTE or PROVIDED");
+    if (a->reserved != 0) return fail(c, HRMS_E_INVAL, "reserved must be 0");
+    if (a->variant == HRMS_EQ1 || a->variant == HRMS_MAX)
+        return fail(c, HRMS_E_UNSUPPORTED, "the 2D sum is implemented for FREQBIN and GREEDY");
+    if (device_ptrs) {
+        if (!a->x) return fail(c, HRMS_E_INVAL, "x is NULL");
+        if (reinterpret_cast<uintptr_t>(a->x) % 16)
+            return fail(c, HRMS_E_INVAL, "x must be 16-byte aligned");
+        if ((a->ld * dtype_bytes(a->dtype)) % 16)
+            return fail(c, HRMS_E_INVAL, "ld * element size must be a multiple of 16 bytes");
+        if (!a->stats) return fail(c, HRMS_E_INVAL, "stats is NULL");
+        if ((a->out_mask & HRMS_OUT_H) && !a->h)
+            return fail(c, HRMS_E_INVAL, "h is NULL but HRMS_OUT_H is set");
+        if ((a->out_mask & HRMS_OUT_MAXSNR) && !a->max_snr)
+            return fail(c, HRMS_E_INVAL, "max_snr is NULL but HRMS_OUT_MAXSNR is set");
+        if ((a->out_mask & HRMS_OUT_BESTH) && !a->best_h)
+            return fail(c, HRMS_E_INVAL, "best_h is NULL but HRMS_OUT_BESTH is set");
+    }
+    return HRMS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Layout
+// ---------------------------------------------------------------------------
+
+int64_t plane_len_1d(int variant, int64_t n, int l) { return variant == HRMS_EQ1 ? n : (n >> l); }
+
+int64_t layout_1d_into(const hrms_run1d_args* a, int64_t* plane_offsets)
+{
+    int64_t off = 0;
+    for (int s = 0; s < a->n_spectra; ++s) {
+        const int64_t n = a->offsets[s + 1] - a->offsets[s];
+        const int nl = levels_of_hmax(a->hmax ? a->hmax[s] : a->hmax_all);
+        for (int l = 0; l < HRMS_MAX_LEVELS; ++l) {
+            int64_t o = -1;
+            if (l < nl) {
+                o = off;
+                off += plane_len_1d(a->variant, n, l);
+            }
+            if (plane_offsets) plane_offsets[(int64_t)s * HRMS_MAX_LEVELS + l] = o;
+        }
+    }
+    return off;
+}
+
+int64_t layout_2d_into(const hrms_run2d_args* a, int64_t* plane_offsets)
+{
+    const int nl = levels_of_hmax(a->hmax);
+    const int64_t rows = 2 * (int64_t)a->zmax + 1;
+    int64_t off = 0;
+    for (int l = 0; l < HRMS_MAX_LEVELS; ++l) {
+        int64_t o = -1;
+        if (l < nl) {
+            o = off;
+            off += rows * ((int64_t)a->nf >> l);
+        }
+        if (plane_offsets) plane_offsets[l] = o;
+    }
+    return off;
+}
+
+// ---------------------------------------------------------------------------
+// Plans
+// ---------------------------------------------------------------------------
+
+Shape1D default_shape(int variant)
+{
+    if (variant == HRMS_EQ1) return Shape1D{256, 8, 4096};
+    return Shape1D{256, 8, 4096};
+}
+
+// Bins a tile stages: harmonic spans, counted once where they overlap.
+int64_t tile_cost(int variant, int64_t n, int nlev, int64_t a, int64_t t)
+{
+    const int64_t aend = std::min(a + t, n);
+    if (variant == HRMS_EQ1) {
+        const int64_t lh = (int64_t)1 << (nlev - 1);
+        return (aend - a) * (lh + 1) / 2 + lh;
+    }
+    int lt = 0;
+    while (lt + 1 < nlev && a < (n >> (lt + 1))) ++lt;
+    const int ht = 1 << lt;
+    int64_t cost = 0, covered = 0;
+    for (int i = 1; i <= ht; ++i) {
+        int li = 0;
+        while ((1 << li) < i) ++li;
+        const int64_t hi = std::min(aend, n >> li);
+        if (hi <= a) continue;
+        const int64_t lo_p = i * a, hi_p = i * (hi - 1) + i;
+        const int64_t start = std::max(lo_p, covered);
+        if (hi_p > start) cost += hi_p - start;
+        covered = std::max(covered, hi_p);
+    }
+    return cost;
+}
+
+template <typename T>
+hipError_t upload(DeviceBuf& b, const std::vector<T>& v, hipStream_t s)
+{
+    hipError_t e = b.ensure(v.size() * sizeof(T));
+    if (e != hipSuccess || v.empty()) return e;
+    return hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+}
+
+int build_plan_1d(hrms_ctx* c, const hrms_run1d_args* a, const Shape1D& shape, Plan1D* P,
+                  hipStream_t stream)
+{
+    const int ns = a->n_spectra;
+    P->offsets.assign(a->offsets, a->offsets + ns + 1);
+    P->nlev.resize(ns);
+    for (int s = 0; s < ns; ++s)
+        P->nlev[s] = (uint8_t)levels_of_hmax(a->hmax ? a->hmax[s] : a->hmax_all);
+    P->variant = a->variant;
+    P->dtype = a->dtype;
+    P->shape = shape;
+
+    std::vector<int64_t> poff((size_t)ns * HRMS_MAX_LEVELS);
+    layout_1d_into(a, poff.data());
+    P->spec.resize(ns);
+    for (int s = 0; s < ns; ++s) {
+        SpecDesc& d = P->spec[s];
+        d.xoff = a->offsets[s];
+        d.ooff = a->offsets[s];
+        for (int l = 0; l < kMaxLevels; ++l) d.hoff[l] = poff[(size_t)s * HRMS_MAX_LEVELS + l];
+        d.n = (int32_t)(a->offsets[s + 1] - a->offsets[s]);
+        d.nlev = P->nlev[s];
+    }
+
+    // tiles, most expensive first (ties by spectrum then position)
+    const int64_t T = (int64_t)shape.wg * shape.r;
+    struct Costed {
+        int64_t cost;
+        Tile t;
+    };
+    std::vector<Costed> ct;
+    for (int s = 0; s < ns; ++s) {
+        const int64_t n = P->spec[s].n;
+        for (int64_t t0 = 0; t0 < n; t0 += T)
+            ct.push_back({tile_cost(a->variant, n, P->nlev[s], t0, T), Tile{s, (int32_t)t0}});
+    }
+    std::stable_sort(ct.begin(), ct.end(),
+                     [](const Costed& x, const Costed& y) { return x.cost > y.cost; });
+    P->tiles.resize(ct.size());
+    for (size_t k = 0; k < ct.size(); ++k) P->tiles[k] = ct[k].t;
+
+    // statistics segments
+    P->segs.clear();
+    P->seg_first.assign(ns + 1, 0);
+    for (int s = 0; s < ns; ++s) {
+        P->seg_first[s] = (int32_t)P->segs.size();
+        const int64_t n = P->spec[s].n;
+        for (int64_t b = 0; b < n; b += kStatsSeg)
+            P->segs.push_back(Seg{s, (int32_t)b, (int32_t)std::min<int64_t>(kStatsSeg, n - b), 0});
+    }
+    P->seg_first[ns] = (int32_t)P->segs.size();
+
+    const int per_cu = hrms1d_max_blocks_per_cu(a->variant, a->dtype, shape);
+    if (per_cu <= 0) return fail(c, HRMS_E_HIP, "occupancy query failed for the 1D kernel");
+    P->grid = (int)std::min<int64_t>((int64_t)P->tiles.size(), (int64_t)c->cu_count * per_cu);
+
+    hipError_t e;
+    if ((e = upload(P->d_spec, P->spec, stream)) != hipSuccess) return hip_fail(c, e, "upload spec");
+    if ((e = upload(P->d_tiles, P->tiles, stream)) != hipSuccess)
+        return hip_fail(c, e, "upload tiles");
+    if ((e = upload(P->d_segs, P->segs, stream)) != hipSuccess) return hip_fail(c, e, "upload segs");
+    if ((e = upload(P->d_seg_first, P->seg_first, stream)) != hipSuccess)
+        return hip_fail(c, e, "upload seg_first");
+    if ((e = P->d_partial.ensure(P->segs.size() * 2 * sizeof(double))) != hipSuccess)
+        return hip_fail(c, e, "alloc partials");
+    if ((e = P->d_consts.ensure((size_t)ns * kMaxLevels * sizeof(LevelConst))) != hipSuccess)
+        return hip_fail(c, e, "alloc consts");
+    if ((e = P->d_counter.ensure(sizeof(unsigned int) * 4)) != hipSuccess)
+        return hip_fail(c, e, "alloc counter");
+    P->uploaded = true;
+    return HRMS_OK;
+}
+
+bool same_signature(const Plan1D& P, const hrms_run1d_args* a, const Shape1D& shape)
+{
+    if (P.variant != a->variant || P.dtype != a->dtype) return false;
+    if (P.shape.wg != shape.wg || P.shape.r != shape.r || P.shape.chunk != shape.chunk)
+        return false;
+    if ((int)P.nlev.size() != a->n_spectra) return false;
+    if (std::memcmp(P.offsets.data(), a->offsets, (a->n_spectra + 1) * sizeof(int64_t)) != 0)
+        return false;
+    for (int s = 0; s < a->n_spectra; ++s)
+        if (P.nlev[s] != levels_of_hmax(a->hmax ? a->hmax[s] : a->hmax_all)) return false;
+    return true;
+}
+
+int get_plan_1d(hrms_ctx* c, const hrms_run1d_args* a, const Shape1D& shape, hipStream_t stream,
+                Plan1D** out)
+{
+    for (size_t k = 0; k < c->plans.size(); ++k) {
+        if (same_signature(*c->plans[k], a, shape)) {
+            std::unique_ptr<Plan1D> p = std::move(c->plans[k]);
+            c->plans.erase(c->plans.begin() + (long)k);
+            c->plans.push_back(std::move(p));
+            *out = c->plans.back().get();
+            return HRMS_OK;
+        }
+    }
+    std::unique_ptr<Plan1D> p(new (std::nothrow) Plan1D());
+    if (!p) return fail(c, HRMS_E_NOMEM, "host allocation failed");
+    int st = build_plan_1d(c, a, shape, p.get(), stream);
+    if (st != HRMS_OK) return st;
+    if ((int)c->plans.size() >= kPlanCache) {
+        // plans still referenced by queued work must outlive it
+        (void)hipStreamSynchronize(stream);
+        c->plans.erase(c->plans.begin());
+    }
+    c->plans.push_back(std::move(p));
+    *out = c->plans.back().get();
+    return HRMS_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+const char* hrms_strerror(int status)
+{
+    switch (status) {
+    case HRMS_OK: return "success";
+    case HRMS_E_INVAL: return "invalid argument";
+    case HRMS_E_UNSUPPORTED: return "unsupported request";
+    case HRMS_E_NODEVICE: return "no usable gfx950 device";
+    case HRMS_E_NOMEM: return "out of memory";
+    case HRMS_E_HIP: return "HIP runtime error";
+    default: return "unknown status";
+    }
+}
+
+const char* hrms_last_error(hrms_handle h)
+{
+    if (!h) return g_last_error.c_str();
+    return h->err.c_str();
+}
+
+int hrms_create(hrms_handle* out, int device_ordinal, const char* tune_cache_path)
+{
+    if (!out) return fail(nullptr, HRMS_E_INVAL, "out is NULL");
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count <= 0)
+        return fail(nullptr, HRMS_E_NODEVICE, "no HIP device is visible");
+    if (device_ordinal < 0 || device_ordinal >= count)
+        return fail(nullptr, HRMS_E_NODEVICE, "device ordinal out of range");
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, device_ordinal);
+    if (e != hipSuccess) return fail(nullptr, HRMS_E_NODEVICE, hipGetErrorString(e));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(nullptr, HRMS_E_NODEVICE,
+                    std::string("device is ") + prop.gcnArchName + ", not gfx950");
+    hrms_ctx* c = new (std::nothrow) hrms_ctx();
+    if (!c) return fail(nullptr, HRMS_E_NOMEM, "host allocation failed");
+    c->device = device_ordinal;
+    c->cu_count = prop.multiProcessorCount;
+    if (tune_cache_path) c->tune_path = tune_cache_path;
+    *out = c;
+    return HRMS_OK;
+}
+
+int hrms_destroy(hrms_handle h)
+{
+    if (!h) return HRMS_OK;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(h->device);
+    (void)hipDeviceSynchronize();
+    h->plans.clear();
+    (void)hipSetDevice(cur);
+    delete h;
+    return HRMS_OK;
+}
+
+int hrms_layout_1d(const hrms_run1d_args* a, int64_t* plane_offsets, int64_t* h_total_floats)
+{
+    int st = validate_1d(nullptr, a, false);
+    if (st != HRMS_OK) return st;
+    const int64_t total = layout_1d_into(a, plane_offsets);
+    if (h_total_floats) *h_total_floats = total;
+    return HRMS_OK;
+}
+
+int hrms_layout_2d(const hrms_run2d_args* a, int64_t* plane_offsets, int64_t* h_total_floats)
+{
+    int st = validate_2d(nullptr, a, false);
+    if (st != HRMS_OK) return st;
+    const int64_t total = layout_2d_into(a, plane_offsets);
+    if (h_total_floats) *h_total_floats = total;
+    return HRMS_OK;
+}
+
+int hrms_run_1d(hrms_handle h, const hrms_run1d_args* a, void* hip_stream)
+{
+    if (!h) return fail(nullptr, HRMS_E_INVAL, "handle is NULL");
+    h->err.clear();
+    int st = validate_1d(h, a, true);
+    if (st != HRMS_OK) return st;
+    hipError_t e = hipSetDevice(h->device);
+    if (e != hipSuccess) return hip_fail(h, e, "hipSetDevice");
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const Shape1D shape = default_shape(a->variant);
+    Plan1D* P = nullptr;
+    st = get_plan_1d(h, a, shape, stream, &P);
+    if (st != HRMS_OK) return st;
+
+    const bool compute = a->stats_mode == HRMS_STATS_COMPUTE;
+    if (compute) {
+        StatsParams sp{a->x, (const SpecDesc*)P->d_spec.p, (const Seg*)P->d_segs.p,
+                       (double*)P->d_partial.p, (int32_t)P->segs.size()};
+        if ((e = launch_stats_partial(a->dtype, sp, stream)) != hipSuccess)
+            return hip_fail(h, e, "statistics launch");
+    }
+    ConstsParams cp{};
+    cp.spec = (const SpecDesc*)P->d_spec.p;
+    cp.segs = (const Seg*)P->d_segs.p;
+    cp.seg_first = (const int32_t*)P->d_seg_first.p;
+    cp.partial = (const double*)P->d_partial.p;
+    cp.stats = a->stats;
+    cp.consts = (LevelConst*)P->d_consts.p;
+    cp.user_consts = a->snr_consts;
+    cp.counter = (unsigned int*)P->d_counter.p;
+    cp.n_spec = a->n_spectra;
+    cp.variant = a->variant;
+    cp.compute_stats = compute ? 1 : 0;
+    if ((e = launch_consts(cp, stream)) != hipSuccess) return hip_fail(h, e, "constants launch");
+
+    if (a->out_mask != 0) {
+        Run1DParams rp{};
+        rp.x = a->x;
+        rp.spec = (const SpecDesc*)P->d_spec.p;
+        rp.tiles = (const Tile*)P->d_tiles.p;
+        rp.consts = (const LevelConst*)P->d_consts.p;
+        rp.h = a->h;
+        rp.max_snr = a->max_snr;
+        rp.best_h = a->best_h;
+        rp.counter = (unsigned int*)P->d_counter.p;
+        rp.ntiles = (int32_t)P->tiles.size();
+        rp.out_mask = a->out_mask;
+        if ((e = launch_hrms1d(a->variant, a->dtype, shape, rp, P->grid, stream)) != hipSuccess)
+            return hip_fail(h, e, "harmonic-sum launch");
+    }
+    return HRMS_OK;
+}
+
+int hrms_run_2d(hrms_handle h, const hrms_run2d_args* a, void* hip_stream)
+{
+    (void)hip_stream;
+    if (!h) return fail(nullptr, HRMS_E_INVAL, "handle is NULL");
+    h->err.clear();
+    int st = validate_2d(h, a, true);
+    if (st != HRMS_OK) return st;
+    return fail(h, HRMS_E_UNSUPPORTED, "2D sum not built yet");
+}
+
+int hrms_quantize(hrms_handle h, const hrms_quantize_args* a, void* hip_stream)
+{
+    (void)hip_stream;
+    (void)a;
+    if (!h) return fail(nullptr, HRMS_E_INVAL, "handle is NULL");
+    return fail(h, HRMS_E_UNSUPPORTED, "quantisation not built yet");
+}
+
+}  // extern "C"

@@ -1,0 +1,122 @@
+// hrms_internal.h -- structures shared by the host runtime (hrms_abi.cpp) and
+// the gfx950 kernels (hrms_kernels.hip). Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace hrms {
+
+constexpr int kMaxLevels = 6;
+
+// One spectrum of a 1D batch (or one row group of a plane), as the kernels see it.
+struct SpecDesc {
+    int64_t xoff;               // first input bin in x (elements)
+    int64_t ooff;               // first bin of max_snr / best_h
+    int64_t hoff[kMaxLevels];   // first float of each level plane in h, -1 if absent
+    int32_t n;                  // bins
+    int32_t nlev;               // levels: log2(Hmax) + 1
+};
+
+// A tile of consecutive outputs [start, start + T) of one spectrum.
+struct Tile {
+    int32_t spec;
+    int32_t start;
+};
+
+// A segment of one spectrum for the statistics reduction.
+struct Seg {
+    int32_t spec;
+    int32_t start;
+    int32_t len;
+    int32_t pad;
+};
+
+// Per-level constants of one spectrum: null mean, inverse null spread and the
+// level's scale fl32(1 / sqrt(H)).
+struct LevelConst {
+    float m;
+    float q;
+    float rh;
+    float pad;
+};
+
+struct Run1DParams {
+    const void* x;
+    const SpecDesc* spec;
+    const Tile* tiles;
+    const LevelConst* consts;   // [n_spec][kMaxLevels]
+    float* h;
+    float* max_snr;
+    uint8_t* best_h;
+    unsigned int* counter;      // work counter of the persistent grid
+    int32_t ntiles;
+    uint32_t out_mask;
+};
+
+struct StatsParams {
+    const void* x;
+    const SpecDesc* spec;
+    const Seg* segs;
+    double* partial;            // [nsegs][2]
+    int32_t nsegs;
+};
+
+struct ConstsParams {
+    const SpecDesc* spec;
+    const Seg* segs;            // segments of each spectrum are contiguous
+    const int32_t* seg_first;   // [n_spec + 1]
+    const double* partial;
+    double* stats;              // [n_spec][2]
+    LevelConst* consts;         // [n_spec][kMaxLevels]
+    float* user_consts;         // optional [n_spec][kMaxLevels][2]
+    unsigned int* counter;      // reset to 0 for the following persistent launch
+    int32_t n_spec;
+    int32_t variant;
+    int32_t compute_stats;      // 1: reduce partials into stats; 0: read stats
+};
+
+struct Run2DParams {
+    const void* x;
+    int64_t ld;
+    const LevelConst* consts;   // [kMaxLevels]
+    float* h;
+    float* max_snr;
+    uint8_t* best_h;
+    int64_t hoff[kMaxLevels];
+    int32_t nf;
+    int32_t zmax;
+    int32_t nlev;
+    uint32_t out_mask;
+};
+
+struct QuantParams {
+    const float* x;
+    const SpecDesc* spec;       // xoff = first bin, n = bins
+    const Seg* segs;
+    const double* stats;        // raw (mu, sigma) per spectrum
+    double* stats_out;          // (1, sigma / mu)
+    void* y;
+    int32_t nsegs;
+    int32_t n_spec;
+};
+
+// Launch shapes of the 1D harmonic-sum kernel family.
+struct Shape1D {
+    int wg;        // threads per workgroup
+    int r;         // outputs per thread (tile = wg * r outputs)
+    int chunk;     // input bins staged in LDS per step
+};
+
+// Kernel launchers (hrms_kernels.hip). Return hipSuccess or the launch error.
+hipError_t launch_stats_partial(int dtype, const StatsParams& p, hipStream_t s);
+hipError_t launch_consts(const ConstsParams& p, hipStream_t s);
+hipError_t launch_hrms1d(int variant, int dtype, const Shape1D& shape, const Run1DParams& p,
+                         int grid, hipStream_t s);
+int hrms1d_max_blocks_per_cu(int variant, int dtype, const Shape1D& shape);
+bool hrms1d_shape_supported(int variant, const Shape1D& shape);
+hipError_t launch_hrms2d(int variant, int dtype, const Run2DParams& p, hipStream_t s);
+hipError_t launch_quantize(int dtype, const QuantParams& p, hipStream_t s);
+
+}  // namespace hrms

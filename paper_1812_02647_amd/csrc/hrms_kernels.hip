@@ -1,0 +1,633 @@
+// hrms_kernels.hip -- gfx950 kernels of the incoherent harmonic sum.
+//
+// Paper: K. Adamek and W. Armour, "A GPU implementation of the harmonic sum
+// algorithm" (arXiv:1812.02647); eq. (1) in Sec. 1, eq. (2)-(4) in Sec. 2.
+//
+// Design (memory-bound; no matrix cores):
+//   * A tile is T = WG * R consecutive outputs [a, a + T) of one spectrum; thread
+//     t owns outputs a + r * WG + t, r < R, and keeps their running sums, best
+//     SNR and best level (and Greedy's offset j) in registers.
+//   * Harmonic i of the tile reads the contiguous span [i a, i (a + T)) (plus up
+//     to i - 1 bins of window). The tile streams the union of these spans
+//     through LDS in chunks of C bins (+ a 32-bin halo for the windows of
+//     eq. (2) and (4)), loaded with 16-byte coalesced loads, so the stride-i
+//     gather of eq. (2)-(4) never reaches HBM or L2 directly. Spans of
+//     neighbouring harmonics overlap once i T >= a, and are then staged once.
+//   * Position i n of output n lies in exactly one chunk, chunks are visited in
+//     increasing position and harmonics in increasing i inside a chunk, so every
+//     output adds its harmonics in the order i = 1..H of the equations.
+//   * A level snapshot (h = S * fl32(1/sqrt(H)), SNR, best level) is taken when
+//     i reaches a power of two.
+//   * LDS holds FP32 whatever the storage type; a 1-in-32 padding keeps strided
+//     reads (stride i) nearly free of bank conflicts.
+//   * The grid is persistent: workgroups pull tiles from a cost-sorted list
+//     through one atomic counter (the paper's load-balancing concern, Sec. 1).
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstdint>
+
+#include "hrms_internal.h"
+
+namespace hrms {
+namespace {
+
+constexpr int kEq1 = 0, kMax = 1, kFreqbin = 2, kGreedy = 3;
+constexpr int kF32 = 0, kF16 = 1, kBF16 = 2;
+constexpr int kHalo = 32;
+
+template <int DT>
+struct Elem {
+    static constexpr int kBytes = DT == kF32 ? 4 : 2;
+    static constexpr int kVec = 16 / kBytes;   // elements per 16-byte load
+};
+
+__device__ __forceinline__ float h2f(uint32_t bits16)
+{
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)bits16);
+}
+
+__device__ __forceinline__ float bf2f(uint32_t bits16) { return __uint_as_float(bits16 << 16); }
+
+template <int DT>
+__device__ __forceinline__ float load_scalar(const void* base, int64_t idx)
+{
+    if constexpr (DT == kF32) {
+        return static_cast<const float*>(base)[idx];
+    } else if constexpr (DT == kF16) {
+        return h2f(static_cast<const uint16_t*>(base)[idx]);
+    } else {
+        return bf2f(static_cast<const uint16_t*>(base)[idx]);
+    }
+}
+
+// Loads the kVec elements starting at absolute element index `abs` (a multiple
+// of kVec); elements outside [lo, hi) read as 0.
+template <int DT>
+__device__ __forceinline__ void load_vec(const void* base, int64_t abs, int64_t lo, int64_t hi,
+                                         float (&v)[Elem<DT>::kVec])
+{
+    constexpr int V = Elem<DT>::kVec;
+    if (abs >= lo && abs + V <= hi) {
+        const uint4 u = *reinterpret_cast<const uint4*>(static_cast<const char*>(base) +
+                                                        abs * Elem<DT>::kBytes);
+        const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+        if constexpr (DT == kF32) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[e] = __uint_as_float(w[e]);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                if constexpr (DT == kF16) {
+                    v[2 * e] = h2f(w[e] & 0xffffu);
+                    v[2 * e + 1] = h2f(w[e] >> 16);
+                } else {
+                    v[2 * e] = bf2f(w[e] & 0xffffu);
+                    v[2 * e + 1] = bf2f(w[e] >> 16);
+                }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            const int64_t k = abs + e;
+            v[e] = (k >= lo && k < hi) ? load_scalar<DT>(base, k) : 0.0f;
+        }
+    }
+}
+
+// LDS index of chunk-relative bin k: one pad word per 32 bins.
+__device__ __forceinline__ int pidx(int k) { return k + (k >> 5); }
+
+// Level index of harmonic i: the smallest l with i <= 2^l.
+__device__ __forceinline__ int level_of(int i) { return 32 - __clz(i - 1); }
+
+// Stages input bins [p0, p0 + NVEC * kVec) of a spectrum into LDS (FP32).
+template <int DT, int WG, int NVEC>
+__device__ __forceinline__ void stage_chunk(float* lds, const void* x, int64_t xoff, int n_bins,
+                                            int p0)
+{
+    constexpr int V = Elem<DT>::kVec;
+    constexpr int VPT = (NVEC + WG - 1) / WG;
+    float v[VPT][V];
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+        const int vi = u * WG + (int)threadIdx.x;
+        if (vi < NVEC) load_vec<DT>(x, xoff + p0 + (int64_t)vi * V, xoff, xoff + n_bins, v[u]);
+    }
+    __syncthreads();  // the previous chunk's readers are done
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+        const int vi = u * WG + (int)threadIdx.x;
+        if (vi < NVEC) {
+#pragma unroll
+            for (int e = 0; e < V; ++e) lds[pidx(vi * V + e)] = v[u][e];
+        }
+    }
+    __syncthreads();
+}
+
+// Chunk start for absolute alignment of the 16-byte loads.
+template <int DT>
+__device__ __forceinline__ int align_chunk(int64_t xoff, int p)
+{
+    constexpr int V = Elem<DT>::kVec;
+    return p - (int)((xoff + p) & (V - 1));
+}
+
+// --------------------------------------------------------------------------
+// eq. (2)-(4): outputs indexed by the fundamental.
+// --------------------------------------------------------------------------
+template <int VAR, int DT, int WG, int R, int C>
+__global__ __launch_bounds__(WG) void k_hrms1d_fund(const Run1DParams p)
+{
+    constexpr int V = Elem<DT>::kVec;
+    static_assert(C % V == 0 && kHalo % V == 0, "chunk must be a multiple of the vector");
+    constexpr int NVEC = (C + kHalo) / V;
+    constexpr int NSTAGE = ((NVEC + WG - 1) / WG) * WG * V;
+    constexpr int T = WG * R;
+    __shared__ float lds[NSTAGE + (NSTAGE >> 5) + 1];
+    __shared__ float s_m[kMaxLevels], s_q[kMaxLevels], s_rh[kMaxLevels];
+    __shared__ int64_t s_hoff[kMaxLevels];
+    __shared__ int s_item;
+
+    const int tid = (int)threadIdx.x;
+    for (;;) {
+        if (tid == 0) s_item = (int)atomicAdd(p.counter, 1u);
+        __syncthreads();
+        const int item = s_item;
+        if (item >= p.ntiles) break;
+        const Tile tl = p.tiles[item];
+        const SpecDesc sd = p.spec[tl.spec];
+        if (tid < kMaxLevels) {
+            const LevelConst lc = p.consts[(int64_t)tl.spec * kMaxLevels + tid];
+            s_m[tid] = lc.m;
+            s_q[tid] = lc.q;
+            s_rh[tid] = lc.rh;
+            s_hoff[tid] = p.spec[tl.spec].hoff[tid];
+        }
+        const int N = sd.n;
+        const int a = tl.start;
+        const int aend = min(a + T, N);
+        int lt = 0;
+        while (lt + 1 < sd.nlev && a < (N >> (lt + 1))) ++lt;
+        const int Ht = 1 << lt;
+
+        float acc[R], best[R];
+        int bl[R], js[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            acc[r] = 0.0f;
+            best[r] = 0.0f;
+            bl[r] = 0;
+            js[r] = 0;
+        }
+
+        int pnext = a;
+        for (;;) {
+            const int p0 = align_chunk<DT>(sd.xoff, pnext);
+            stage_chunk<DT, WG, NVEC>(lds, p.x, sd.xoff, N, p0);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int b0 = a + r * WG;
+                if (b0 < aend) {
+                    const int b1 = min(b0 + WG, aend);
+                    int ilo = 1;
+                    if (p0 > 0 && b1 > 1) ilo = max(1, (p0 + b1 - 2) / (b1 - 1));
+                    int ihi = Ht;
+                    if (b0 > 0) ihi = min(Ht, (p0 + C - 1) / b0);
+                    const int n = b0 + tid;
+                    for (int i = ilo; i <= ihi; ++i) {
+                        const int li = level_of(i);
+                        const int hi = min(b1, N >> li);
+                        const int pos = n < hi ? i * n : p0 + C;
+                        if (pos >= p0 && pos < p0 + C) {
+                            const int k = pos - p0;
+                            float tv;
+                            if constexpr (VAR == kFreqbin) {
+                                tv = lds[pidx(k)];
+                            } else if constexpr (VAR == kMax) {
+                                tv = lds[pidx(k)];
+                                for (int jj = 1; jj < i; ++jj) {
+                                    const float w = lds[pidx(k + jj)];
+                                    tv = w > tv ? w : tv;
+                                }
+                            } else {
+                                if (i == 1) {
+                                    tv = lds[pidx(k)];
+                                } else {
+                                    const int j = js[r];
+                                    const float x0 = lds[pidx(k + j)];
+                                    const float x1 = lds[pidx(k + j + 1)];
+                                    if (x1 > x0) {
+                                        tv = x1;
+                                        js[r] = j + 1;
+                                    } else {
+                                        tv = x0;
+                                    }
+                                }
+                            }
+                            acc[r] = acc[r] + tv;
+                            if ((i & (i - 1)) == 0) {
+                                const float hv = acc[r] * s_rh[li];
+                                if (p.out_mask & 1u) p.h[s_hoff[li] + n] = hv;
+                                const float snr = (hv - s_m[li]) * s_q[li];
+                                if (li == 0 || snr > best[r]) {
+                                    best[r] = snr;
+                                    bl[r] = li;
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+            // next chunk: the lowest position >= p0 + C still needed by any harmonic
+            const int q = p0 + C;
+            int nxt = INT_MAX;
+            for (int i = 1; i <= Ht; ++i) {
+                const int hi = min(aend, N >> level_of(i));
+                if (hi <= a) continue;
+                if (i * (hi - 1) >= q) nxt = min(nxt, max(q, i * a));
+            }
+            if (nxt == INT_MAX) break;
+            pnext = nxt;
+        }
+
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int n = a + r * WG + tid;
+            if (n < aend) {
+                if (p.out_mask & 2u) p.max_snr[sd.ooff + n] = best[r];
+                if (p.out_mask & 4u) p.best_h[sd.ooff + n] = (uint8_t)(1u << bl[r]);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// --------------------------------------------------------------------------
+// eq. (1): output n is the H-th harmonic; term i of level H reads bin
+// round(n i / H). With Lh = Hmax, term i of level H is fraction k / Lh,
+// k = i Lh / H, so every term of every level is one of the Lh bins
+// v_k = x[round(n k / Lh)], k = 1..Lh, and v_k belongs to the levels
+// H >= Lh / 2^tz(k). Bins v_k are met in increasing k, so each level still adds
+// its terms in the order i = 1..H; each level keeps its own sum.
+// --------------------------------------------------------------------------
+template <int DT, int WG, int R, int C>
+__global__ __launch_bounds__(WG) void k_hrms1d_eq1(const Run1DParams p)
+{
+    constexpr int V = Elem<DT>::kVec;
+    static_assert(C % V == 0 && kHalo % V == 0, "chunk must be a multiple of the vector");
+    constexpr int NVEC = (C + kHalo) / V;
+    constexpr int NSTAGE = ((NVEC + WG - 1) / WG) * WG * V;
+    constexpr int T = WG * R;
+    __shared__ float lds[NSTAGE + (NSTAGE >> 5) + 1];
+    __shared__ float s_m[kMaxLevels], s_q[kMaxLevels], s_rh[kMaxLevels];
+    __shared__ int64_t s_hoff[kMaxLevels];
+    __shared__ int s_item;
+
+    const int tid = (int)threadIdx.x;
+    for (;;) {
+        if (tid == 0) s_item = (int)atomicAdd(p.counter, 1u);
+        __syncthreads();
+        const int item = s_item;
+        if (item >= p.ntiles) break;
+        const Tile tl = p.tiles[item];
+        const SpecDesc sd = p.spec[tl.spec];
+        if (tid < kMaxLevels) {
+            const LevelConst lc = p.consts[(int64_t)tl.spec * kMaxLevels + tid];
+            s_m[tid] = lc.m;
+            s_q[tid] = lc.q;
+            s_rh[tid] = lc.rh;
+            s_hoff[tid] = p.spec[tl.spec].hoff[tid];
+        }
+        const int N = sd.n;
+        const int a = tl.start;
+        const int aend = min(a + T, N);
+        const int nl = sd.nlev;
+        const int sh = nl - 1;
+        const int Lh = 1 << sh;
+        const unsigned half = (unsigned)Lh >> 1;
+
+        float acc[R][kMaxLevels], best[R];
+        int bl[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+#pragma unroll
+            for (int l = 0; l < kMaxLevels; ++l) acc[r][l] = 0.0f;
+            best[r] = 0.0f;
+            bl[r] = 0;
+        }
+
+        // round(n k / Lh), halves up: floor((n k + Lh/2) / Lh)
+        auto posf = [&](int n, int k) -> int {
+            return (int)(((unsigned)n * (unsigned)k + half) >> sh);
+        };
+
+        int pnext = posf(a, 1);
+        for (;;) {
+            const int p0 = align_chunk<DT>(sd.xoff, pnext);
+            stage_chunk<DT, WG, NVEC>(lds, p.x, sd.xoff, N, p0);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int b0 = a + r * WG;
+                if (b0 < aend) {
+                    const int b1 = min(b0 + WG, aend);
+                    // pos(n, k) >= p0  <=>  n k >= p0 Lh - Lh/2
+                    int klo = 1;
+                    const int64_t tlo = (int64_t)p0 * Lh - half;
+                    if (tlo > 0 && b1 > 1) {
+                        const int64_t c = (tlo + (b1 - 1) - 1) / (b1 - 1);
+                        klo = (int)(c > Lh + 1 ? Lh + 1 : c);
+                    }
+                    // pos(n, k) < p0 + C  <=>  n k < (p0 + C) Lh - Lh/2
+                    int khi = Lh;
+                    if (b0 > 0) {
+                        const int64_t thi = ((int64_t)(p0 + C) * Lh - half - 1) / b0;
+                        khi = (int)(thi < Lh ? thi : Lh);
+                    }
+                    const int n = b0 + tid;
+                    for (int k = klo; k <= khi; ++k) {
+                        const int pos = n < b1 ? posf(n, k) : p0 + C;
+                        if (pos >= p0 && pos < p0 + C) {
+                            const float v = lds[pidx(pos - p0)];
+                            const int lmin = sh - __builtin_ctz((unsigned)k);
+#pragma unroll
+                            for (int l = 0; l < kMaxLevels; ++l) {
+                                if (l >= lmin && l < nl) acc[r][l] = acc[r][l] + v;
+                            }
+                            if (k == Lh) {
+#pragma unroll
+                                for (int l = 0; l < kMaxLevels; ++l) {
+                                    if (l < nl) {
+                                        const float hv = acc[r][l] * s_rh[l];
+                                        if (p.out_mask & 1u) p.h[s_hoff[l] + n] = hv;
+                                        const float snr = (hv - s_m[l]) * s_q[l];
+                                        if (l == 0 || snr > best[r]) {
+                                            best[r] = snr;
+                                            bl[r] = l;
+                                        }
+                                    }
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+            const int q = p0 + C;
+            int nxt = INT_MAX;
+            for (int k = 1; k <= Lh; ++k) {
+                if (posf(aend - 1, k) >= q) nxt = min(nxt, max(q, posf(a, k)));
+            }
+            if (nxt == INT_MAX) break;
+            pnext = nxt;
+        }
+
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int n = a + r * WG + tid;
+            if (n < aend) {
+                if (p.out_mask & 2u) p.max_snr[sd.ooff + n] = best[r];
+                if (p.out_mask & 4u) p.best_h[sd.ooff + n] = (uint8_t)(1u << bl[r]);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// --------------------------------------------------------------------------
+// Statistics: FP64 sums of x and x^2 per segment, in a fixed order, so that
+// repeated runs give identical bits.
+// --------------------------------------------------------------------------
+constexpr int kStatsWG = 256;
+
+template <int DT>
+__global__ __launch_bounds__(kStatsWG) void k_stats_partial(const StatsParams p)
+{
+    // Thread t sums bins start + t + k * WG in increasing k: the order depends
+    // only on positions inside the spectrum, not on where the batch packs it.
+    constexpr int U = 8;
+    __shared__ double s_red[2][kStatsWG / 64];
+    const Seg sg = p.segs[blockIdx.x];
+    const SpecDesc sd = p.spec[sg.spec];
+    const int tid = (int)threadIdx.x;
+    const int64_t base = sd.xoff + sg.start;
+    double s1 = 0.0, s2 = 0.0;
+    int e = tid;
+    for (; e + (U - 1) * kStatsWG < sg.len; e += U * kStatsWG) {
+        float v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = load_scalar<DT>(p.x, base + e + u * kStatsWG);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const double d = (double)v[u];
+            s1 = s1 + d;
+            s2 = s2 + d * d;
+        }
+    }
+    for (; e < sg.len; e += kStatsWG) {
+        const double d = (double)load_scalar<DT>(p.x, base + e);
+        s1 = s1 + d;
+        s2 = s2 + d * d;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        s1 = s1 + __shfl_xor(s1, off, 64);
+        s2 = s2 + __shfl_xor(s2, off, 64);
+    }
+    if ((tid & 63) == 0) {
+        s_red[0][tid >> 6] = s1;
+        s_red[1][tid >> 6] = s2;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double t1 = 0.0, t2 = 0.0;
+        for (int w = 0; w < kStatsWG / 64; ++w) {
+            t1 = t1 + s_red[0][w];
+            t2 = t2 + s_red[1][w];
+        }
+        p.partial[2 * (int64_t)blockIdx.x] = t1;
+        p.partial[2 * (int64_t)blockIdx.x + 1] = t2;
+    }
+}
+
+// Null mean and spread of h_H (see hrms.h): evaluated in FP64 in a fixed
+// operation order, then rounded once to FP32.
+__device__ void level_consts(int variant, double mu, double sigma, int H, double* m_out,
+                             double* q_out)
+{
+    const double rh = sqrt((double)H);
+    double mean_s, var_s;
+    if (variant == kEq1 || variant == kFreqbin) {
+        mean_s = (double)H * mu;
+        var_s = (double)H * (sigma * sigma);
+    } else if (variant == kMax) {
+        // maximum of i exponential bins: mean mu + sigma (Hn_i - 1),
+        // variance sigma^2 Psi_i (Renyi's representation of order statistics)
+        double hn = 0.0, psi = 0.0, sum_mean = 0.0, sum_psi = 0.0;
+        for (int i = 1; i <= H; ++i) {
+            hn = hn + 1.0 / (double)i;
+            psi = psi + 1.0 / ((double)i * (double)i);
+            sum_mean = sum_mean + (mu + sigma * (hn - 1.0));
+            sum_psi = sum_psi + psi;
+        }
+        mean_s = sum_mean;
+        var_s = (sigma * sigma) * sum_psi;
+    } else {
+        // Greedy: one bin, then H - 1 maxima of two fresh bins
+        mean_s = mu + (double)(H - 1) * (mu + 0.5 * sigma);
+        var_s = (sigma * sigma) * (1.0 + 1.25 * (double)(H - 1));
+    }
+    const double m = mean_s / rh;
+    const double s = sqrt(var_s) / rh;
+    *m_out = m;
+    *q_out = s > 0.0 ? 1.0 / s : 0.0;
+}
+
+__global__ __launch_bounds__(64) void k_consts(const ConstsParams p)
+{
+    const int s = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (s == 0 && p.counter) *p.counter = 0u;
+    if (s >= p.n_spec) return;
+    const SpecDesc sd = p.spec[s];
+    double mu, sigma;
+    if (p.compute_stats) {
+        double t1 = 0.0, t2 = 0.0;
+        for (int g = p.seg_first[s]; g < p.seg_first[s + 1]; ++g) {
+            t1 = t1 + p.partial[2 * (int64_t)g];
+            t2 = t2 + p.partial[2 * (int64_t)g + 1];
+        }
+        const double nb = (double)sd.n;
+        mu = t1 / nb;
+        double var = t2 / nb - mu * mu;
+        if (var < 0.0) var = 0.0;
+        sigma = sqrt(var);
+        p.stats[2 * (int64_t)s] = mu;
+        p.stats[2 * (int64_t)s + 1] = sigma;
+    } else {
+        mu = p.stats[2 * (int64_t)s];
+        sigma = p.stats[2 * (int64_t)s + 1];
+    }
+    for (int l = 0; l < kMaxLevels; ++l) {
+        float m32 = 0.0f, q32 = 0.0f;
+        if (l < sd.nlev) {
+            double m, q;
+            level_consts(p.variant, mu, sigma, 1 << l, &m, &q);
+            m32 = (float)m;
+            q32 = (float)q;
+        }
+        const float rh = (float)(1.0 / sqrt((double)(1 << l)));
+        p.consts[(int64_t)s * kMaxLevels + l] = LevelConst{m32, q32, rh, 0.0f};
+        if (p.user_consts) {
+            p.user_consts[((int64_t)s * kMaxLevels + l) * 2] = m32;
+            p.user_consts[((int64_t)s * kMaxLevels + l) * 2 + 1] = q32;
+        }
+    }
+}
+
+template <int VAR, int DT, int WG, int R, int C>
+void* fund_kernel()
+{
+    return reinterpret_cast<void*>(&k_hrms1d_fund<VAR, DT, WG, R, C>);
+}
+
+template <int DT, int WG, int R, int C>
+void* eq1_kernel()
+{
+    return reinterpret_cast<void*>(&k_hrms1d_eq1<DT, WG, R, C>);
+}
+
+// Launch shapes compiled into the library.
+struct ShapeEntry {
+    int wg, r, chunk;
+    void* (*fund[3][3])();   // [variant - 1][dtype]
+    void* (*eq1[3])();
+};
+
+template <int WG, int R, int C>
+constexpr ShapeEntry make_shape()
+{
+    return ShapeEntry{WG,
+                      R,
+                      C,
+                      {{&fund_kernel<kMax, kF32, WG, R, C>, &fund_kernel<kMax, kF16, WG, R, C>,
+                        &fund_kernel<kMax, kBF16, WG, R, C>},
+                       {&fund_kernel<kFreqbin, kF32, WG, R, C>,
+                        &fund_kernel<kFreqbin, kF16, WG, R, C>,
+                        &fund_kernel<kFreqbin, kBF16, WG, R, C>},
+                       {&fund_kernel<kGreedy, kF32, WG, R, C>,
+                        &fund_kernel<kGreedy, kF16, WG, R, C>,
+                        &fund_kernel<kGreedy, kBF16, WG, R, C>}},
+                      {&eq1_kernel<kF32, WG, R, C>, &eq1_kernel<kF16, WG, R, C>,
+                       &eq1_kernel<kBF16, WG, R, C>}};
+}
+
+const ShapeEntry kShapes[] = {
+    make_shape<256, 16, 4096>(),
+    make_shape<256, 8, 4096>(),
+};
+
+const ShapeEntry* find_shape(const Shape1D& s)
+{
+    for (const ShapeEntry& e : kShapes)
+        if (e.wg == s.wg && e.r == s.r && e.chunk == s.chunk) return &e;
+    return nullptr;
+}
+
+void* kernel_for(int variant, int dtype, const ShapeEntry* e)
+{
+    if (!e || dtype < 0 || dtype > 2 || variant < 0 || variant > 3) return nullptr;
+    return variant == kEq1 ? e->eq1[dtype]() : e->fund[variant - 1][dtype]();
+}
+
+}  // namespace
+
+hipError_t launch_stats_partial(int dtype, const StatsParams& p, hipStream_t s)
+{
+    if (p.nsegs <= 0) return hipSuccess;
+    dim3 grid(p.nsegs), block(kStatsWG);
+    switch (dtype) {
+    case kF32: hipLaunchKernelGGL(k_stats_partial<kF32>, grid, block, 0, s, p); break;
+    case kF16: hipLaunchKernelGGL(k_stats_partial<kF16>, grid, block, 0, s, p); break;
+    default: hipLaunchKernelGGL(k_stats_partial<kBF16>, grid, block, 0, s, p); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_consts(const ConstsParams& p, hipStream_t s)
+{
+    const int blocks = (p.n_spec + 63) / 64;
+    hipLaunchKernelGGL(k_consts, dim3(blocks), dim3(64), 0, s, p);
+    return hipGetLastError();
+}
+
+bool hrms1d_shape_supported(int variant, const Shape1D& shape)
+{
+    return kernel_for(variant, kF32, find_shape(shape)) != nullptr;
+}
+
+int hrms1d_max_blocks_per_cu(int variant, int dtype, const Shape1D& shape)
+{
+    void* k = kernel_for(variant, dtype, find_shape(shape));
+    if (!k) return 0;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, shape.wg, 0) != hipSuccess) return 0;
+    return nb;
+}
+
+hipError_t launch_hrms1d(int variant, int dtype, const Shape1D& shape, const Run1DParams& p,
+                         int grid, hipStream_t s)
+{
+    void* k = kernel_for(variant, dtype, find_shape(shape));
+    if (!k) return hipErrorInvalidValue;
+    if (grid <= 0) return hipSuccess;
+    Run1DParams pc = p;
+    void* args[] = {&pc};
+    return hipLaunchKernel(k, dim3(grid), dim3(shape.wg), args, 0, s);
+}
+
+hipError_t launch_hrms2d(int, int, const Run2DParams&, hipStream_t) { return hipErrorNotSupported; }
+
+hipError_t launch_quantize(int, const QuantParams&, hipStream_t) { return hipErrorNotSupported; }
+
+}  // namespace hrms
