@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -62,11 +63,13 @@ struct Plan1D {
     // host mirrors (kept alive for the asynchronous uploads)
     std::vector<SpecDesc> spec;
     std::vector<Tile> tiles;
+    std::vector<int32_t> qbeg;
     std::vector<Seg> segs;
     std::vector<int32_t> seg_first;
     int grid = 0;
+    int nqueues = 1;
     // device
-    DeviceBuf d_spec, d_tiles, d_segs, d_seg_first, d_partial, d_consts, d_counter;
+    DeviceBuf d_spec, d_tiles, d_qbeg, d_segs, d_seg_first, d_partial, d_consts, d_counter;
     bool uploaded = false;
 };
 
@@ -233,8 +236,8 @@ int64_t layout_2d_into(const hrms_run2d_args* a, int64_t* plane_offsets)
 
 Shape1D default_shape(int variant)
 {
-    if (variant == HRMS_EQ1) return Shape1D{256, 8, 4096};
-    return Shape1D{256, 8, 4096};
+    if (variant == HRMS_EQ1) return Shape1D{256, 8, 0};
+    return Shape1D{256, 8, 8192};
 }
 
 // Bins a tile stages: harmonic spans, counted once where they overlap.
@@ -294,22 +297,50 @@ int build_plan_1d(hrms_ctx* c, const hrms_run1d_args* a, const Shape1D& shape, P
         d.nlev = P->nlev[s];
     }
 
-    // tiles, most expensive first (ties by spectrum then position)
+    // Tiles. Spectra are spread over one queue per XCD, balancing their total
+    // cost; a queue lists its spectra one after the other (so the bins of a
+    // spectrum stay in that XCD's L2 while its tiles run), each spectrum's
+    // tiles most expensive first.
     const int64_t T = (int64_t)shape.wg * shape.r;
-    struct Costed {
-        int64_t cost;
-        Tile t;
-    };
-    std::vector<Costed> ct;
+    const int nq = (c->cu_count >= kMaxQueues && c->cu_count % kMaxQueues == 0) ? kMaxQueues : 1;
+    std::vector<std::vector<std::pair<int64_t, Tile>>> per_spec(ns);
+    std::vector<std::pair<int64_t, int>> spec_cost(ns);
     for (int s = 0; s < ns; ++s) {
         const int64_t n = P->spec[s].n;
-        for (int64_t t0 = 0; t0 < n; t0 += T)
-            ct.push_back({tile_cost(a->variant, n, P->nlev[s], t0, T), Tile{s, (int32_t)t0}});
+        int64_t tot = 0;
+        for (int64_t t0 = 0; t0 < n; t0 += T) {
+            const int64_t cst = tile_cost(a->variant, n, P->nlev[s], t0, T);
+            per_spec[s].push_back({cst, Tile{s, (int32_t)t0}});
+            tot += cst;
+        }
+        std::stable_sort(per_spec[s].begin(), per_spec[s].end(),
+                         [](const std::pair<int64_t, Tile>& x, const std::pair<int64_t, Tile>& y) {
+                             return x.first > y.first;
+                         });
+        spec_cost[s] = {tot, s};
     }
-    std::stable_sort(ct.begin(), ct.end(),
-                     [](const Costed& x, const Costed& y) { return x.cost > y.cost; });
-    P->tiles.resize(ct.size());
-    for (size_t k = 0; k < ct.size(); ++k) P->tiles[k] = ct[k].t;
+    std::stable_sort(spec_cost.begin(), spec_cost.end(),
+                     [](const std::pair<int64_t, int>& x, const std::pair<int64_t, int>& y) {
+                         return x.first > y.first;
+                     });
+    std::vector<std::vector<int>> qspec(nq);
+    std::vector<int64_t> qload(nq, 0);
+    for (const auto& sc : spec_cost) {
+        int best = 0;
+        for (int q = 1; q < nq; ++q)
+            if (qload[q] < qload[best]) best = q;
+        qspec[best].push_back(sc.second);
+        qload[best] += sc.first;
+    }
+    P->tiles.clear();
+    P->qbeg.assign(nq + 1, 0);
+    for (int q = 0; q < nq; ++q) {
+        P->qbeg[q] = (int32_t)P->tiles.size();
+        for (int s : qspec[q])
+            for (const auto& ct : per_spec[s]) P->tiles.push_back(ct.second);
+    }
+    P->qbeg[nq] = (int32_t)P->tiles.size();
+    P->nqueues = nq;
 
     // statistics segments
     P->segs.clear();
@@ -324,12 +355,15 @@ int build_plan_1d(hrms_ctx* c, const hrms_run1d_args* a, const Shape1D& shape, P
 
     const int per_cu = hrms1d_max_blocks_per_cu(a->variant, a->dtype, shape);
     if (per_cu <= 0) return fail(c, HRMS_E_HIP, "occupancy query failed for the 1D kernel");
-    P->grid = (int)std::min<int64_t>((int64_t)P->tiles.size(), (int64_t)c->cu_count * per_cu);
+    int64_t grid = std::min<int64_t>((int64_t)P->tiles.size(), (int64_t)c->cu_count * per_cu);
+    if (grid >= nq) grid -= grid % nq;   // every queue gets the same number of workgroups
+    P->grid = (int)std::max<int64_t>(grid, 1);
 
     hipError_t e;
     if ((e = upload(P->d_spec, P->spec, stream)) != hipSuccess) return hip_fail(c, e, "upload spec");
     if ((e = upload(P->d_tiles, P->tiles, stream)) != hipSuccess)
         return hip_fail(c, e, "upload tiles");
+    if ((e = upload(P->d_qbeg, P->qbeg, stream)) != hipSuccess) return hip_fail(c, e, "upload qbeg");
     if ((e = upload(P->d_segs, P->segs, stream)) != hipSuccess) return hip_fail(c, e, "upload segs");
     if ((e = upload(P->d_seg_first, P->seg_first, stream)) != hipSuccess)
         return hip_fail(c, e, "upload seg_first");
@@ -337,7 +371,7 @@ int build_plan_1d(hrms_ctx* c, const hrms_run1d_args* a, const Shape1D& shape, P
         return hip_fail(c, e, "alloc partials");
     if ((e = P->d_consts.ensure((size_t)ns * kMaxLevels * sizeof(LevelConst))) != hipSuccess)
         return hip_fail(c, e, "alloc consts");
-    if ((e = P->d_counter.ensure(sizeof(unsigned int) * 4)) != hipSuccess)
+    if ((e = P->d_counter.ensure(sizeof(unsigned int) * kMaxQueues)) != hipSuccess)
         return hip_fail(c, e, "alloc counter");
     P->uploaded = true;
     return HRMS_OK;
@@ -473,7 +507,14 @@ int hrms_run_1d(hrms_handle h, const hrms_run1d_args* a, void* hip_stream)
     hipError_t e = hipSetDevice(h->device);
     if (e != hipSuccess) return hip_fail(h, e, "hipSetDevice");
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
-    const Shape1D shape = default_shape(a->variant);
+    Shape1D shape = default_shape(a->variant);
+    if (const char* f = std::getenv("HRMS_FORCE_SHAPE")) {
+        // debugging override "wg:r:chunk", ignored unless compiled in
+        Shape1D fs{};
+        if (std::sscanf(f, "%d:%d:%d", &fs.wg, &fs.r, &fs.chunk) == 3 &&
+            hrms1d_shape_supported(a->variant, fs))
+            shape = fs;
+    }
     Plan1D* P = nullptr;
     st = get_plan_1d(h, a, shape, stream, &P);
     if (st != HRMS_OK) return st;
@@ -493,7 +534,7 @@ int hrms_run_1d(hrms_handle h, const hrms_run1d_args* a, void* hip_stream)
     cp.stats = a->stats;
     cp.consts = (LevelConst*)P->d_consts.p;
     cp.user_consts = a->snr_consts;
-    cp.counter = (unsigned int*)P->d_counter.p;
+    cp.counters = (unsigned int*)P->d_counter.p;
     cp.n_spec = a->n_spectra;
     cp.variant = a->variant;
     cp.compute_stats = compute ? 1 : 0;
@@ -508,8 +549,9 @@ int hrms_run_1d(hrms_handle h, const hrms_run1d_args* a, void* hip_stream)
         rp.h = a->h;
         rp.max_snr = a->max_snr;
         rp.best_h = a->best_h;
-        rp.counter = (unsigned int*)P->d_counter.p;
-        rp.ntiles = (int32_t)P->tiles.size();
+        rp.counters = (unsigned int*)P->d_counter.p;
+        rp.qbeg = (const int32_t*)P->d_qbeg.p;
+        rp.nqueues = P->nqueues;
         rp.out_mask = a->out_mask;
         if ((e = launch_hrms1d(a->variant, a->dtype, shape, rp, P->grid, stream)) != hipSuccess)
             return hip_fail(h, e, "harmonic-sum launch");

@@ -42,16 +42,21 @@ struct LevelConst {
     float pad;
 };
 
+// Work queues of the persistent grid: one per XCD (workgroup w starts on queue
+// w % nqueues and moves on to the next queue when its own is drained).
+constexpr int kMaxQueues = 8;
+
 struct Run1DParams {
     const void* x;
     const SpecDesc* spec;
-    const Tile* tiles;
+    const Tile* tiles;          // queue q holds tiles[qbeg[q] .. qbeg[q + 1])
     const LevelConst* consts;   // [n_spec][kMaxLevels]
     float* h;
     float* max_snr;
     uint8_t* best_h;
-    unsigned int* counter;      // work counter of the persistent grid
-    int32_t ntiles;
+    unsigned int* counters;     // [kMaxQueues] tiles taken from each queue
+    const int32_t* qbeg;        // [nqueues + 1]
+    int32_t nqueues;
     uint32_t out_mask;
 };
 
@@ -71,7 +76,7 @@ struct ConstsParams {
     double* stats;              // [n_spec][2]
     LevelConst* consts;         // [n_spec][kMaxLevels]
     float* user_consts;         // optional [n_spec][kMaxLevels][2]
-    unsigned int* counter;      // reset to 0 for the following persistent launch
+    unsigned int* counters;     // [kMaxQueues], reset to 0 for the following launch
     int32_t n_spec;
     int32_t variant;
     int32_t compute_stats;      // 1: reduce partials into stats; 0: read stats
@@ -106,7 +111,8 @@ struct QuantParams {
 struct Shape1D {
     int wg;        // threads per workgroup
     int r;         // outputs per thread (tile = wg * r outputs)
-    int chunk;     // input bins staged in LDS per step
+    int chunk;     // LDS staging buffer in bins (one of two); Max and Greedy
+                   // keep the last 32 for the window past the chunk
 };
 
 // Kernel launchers (hrms_kernels.hip). Return hipSuccess or the launch error.
@@ -116,6 +122,9 @@ hipError_t launch_hrms1d(int variant, int dtype, const Shape1D& shape, const Run
                          int grid, hipStream_t s);
 int hrms1d_max_blocks_per_cu(int variant, int dtype, const Shape1D& shape);
 bool hrms1d_shape_supported(int variant, const Shape1D& shape);
+// Shapes compiled for the variant's kernel family; returns their count and
+// writes up to `cap` of them.
+int hrms1d_shapes(int variant, Shape1D* out, int cap);
 hipError_t launch_hrms2d(int variant, int dtype, const Run2DParams& p, hipStream_t s);
 hipError_t launch_quantize(int dtype, const QuantParams& p, hipStream_t s);
 

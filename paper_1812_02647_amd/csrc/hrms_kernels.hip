@@ -102,30 +102,7 @@ __device__ __forceinline__ int pidx(int k) { return k + (k >> 5); }
 // Level index of harmonic i: the smallest l with i <= 2^l.
 __device__ __forceinline__ int level_of(int i) { return 32 - __clz(i - 1); }
 
-// Stages input bins [p0, p0 + NVEC * kVec) of a spectrum into LDS (FP32).
-template <int DT, int WG, int NVEC>
-__device__ __forceinline__ void stage_chunk(float* lds, const void* x, int64_t xoff, int n_bins,
-                                            int p0)
-{
-    constexpr int V = Elem<DT>::kVec;
-    constexpr int VPT = (NVEC + WG - 1) / WG;
-    float v[VPT][V];
-#pragma unroll
-    for (int u = 0; u < VPT; ++u) {
-        const int vi = u * WG + (int)threadIdx.x;
-        if (vi < NVEC) load_vec<DT>(x, xoff + p0 + (int64_t)vi * V, xoff, xoff + n_bins, v[u]);
-    }
-    __syncthreads();  // the previous chunk's readers are done
-#pragma unroll
-    for (int u = 0; u < VPT; ++u) {
-        const int vi = u * WG + (int)threadIdx.x;
-        if (vi < NVEC) {
-#pragma unroll
-            for (int e = 0; e < V; ++e) lds[pidx(vi * V + e)] = v[u][e];
-        }
-    }
-    __syncthreads();
-}
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // Chunk start for absolute alignment of the 16-byte loads.
 template <int DT>
@@ -135,74 +112,199 @@ __device__ __forceinline__ int align_chunk(int64_t xoff, int p)
     return p - (int)((xoff + p) & (V - 1));
 }
 
+// Raw 16-byte vector of the input (kVec elements) with zeros outside [lo, hi).
+template <int DT>
+__device__ __forceinline__ uint4 load_raw(const void* base, int64_t abs, int64_t lo, int64_t hi)
+{
+    constexpr int V = Elem<DT>::kVec;
+    if (abs >= lo && abs + V <= hi)
+        return *reinterpret_cast<const uint4*>(static_cast<const char*>(base) +
+                                               abs * Elem<DT>::kBytes);
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+        const int64_t k = abs + e;
+        if (k >= lo && k < hi) {
+            if constexpr (DT == kF32) {
+                w[e] = static_cast<const uint32_t*>(base)[k];
+            } else {
+                const uint32_t b = static_cast<const uint16_t*>(base)[k];
+                w[e >> 1] |= b << (16 * (e & 1));
+            }
+        }
+    }
+    return uint4{w[0], w[1], w[2], w[3]};
+}
+
+template <int DT>
+__device__ __forceinline__ void store_raw(float* buf, int k0, const uint4& u)
+{
+    const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+    if constexpr (DT == kF32) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) buf[pidx(k0 + e)] = __uint_as_float(w[e]);
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const float lo = DT == kF16 ? h2f(w[e] & 0xffffu) : bf2f(w[e] & 0xffffu);
+            const float hi = DT == kF16 ? h2f(w[e] >> 16) : bf2f(w[e] >> 16);
+            buf[pidx(k0 + 2 * e)] = lo;
+            buf[pidx(k0 + 2 * e + 1)] = hi;
+        }
+    }
+}
+
+// Register stage of one chunk: VPT 16-byte vectors per thread.
+template <int DT, int WG, int VPT>
+struct Stage {
+    uint4 v[VPT];
+    __device__ __forceinline__ void load(const void* x, int64_t xoff, int n_bins, int p0, int nvec)
+    {
+        constexpr int V = Elem<DT>::kVec;
+#pragma unroll
+        for (int u = 0; u < VPT; ++u) {
+            const int vi = u * WG + (int)threadIdx.x;
+            if (vi < nvec) v[u] = load_raw<DT>(x, xoff + p0 + (int64_t)vi * V, xoff, xoff + n_bins);
+        }
+    }
+    __device__ __forceinline__ void store(float* buf, int nvec) const
+    {
+        constexpr int V = Elem<DT>::kVec;
+#pragma unroll
+        for (int u = 0; u < VPT; ++u) {
+            const int vi = u * WG + (int)threadIdx.x;
+            if (vi < nvec) store_raw<DT>(buf, vi * V, v[u]);
+        }
+    }
+};
+
+// Takes the next tile for this workgroup (thread 0 only): from the current
+// queue while it lasts, then from the following queues in turn.
+__device__ __forceinline__ int take_tile(const Run1DParams& p, int& q, int& visited)
+{
+    while (visited < p.nqueues) {
+        const unsigned k = atomicAdd(&p.counters[q], 1u);
+        const int len = p.qbeg[q + 1] - p.qbeg[q];
+        if ((int)k < len) return p.qbeg[q] + (int)k;
+        q = q + 1 == p.nqueues ? 0 : q + 1;
+        ++visited;
+    }
+    return -1;
+}
+
 // --------------------------------------------------------------------------
 // eq. (2)-(4): outputs indexed by the fundamental.
+//
+// A tile is the T = WG * R outputs [a, aend) of one spectrum; thread t holds
+// outputs a + r WG + t (r < R) in registers. Harmonic i is needed for the
+// outputs n < hi_i = min(aend, floor(N / 2^level(i))) and reads positions i n
+// (+ up to i - 1 bins of window for eq. (2) and (4)).
+//
+// The tile walks harmonic-major: for i = 1..Ht, its valid outputs are cut into
+// pieces [n0, n1) of at most PMAX / i outputs, so that the span i n0 ..
+// i (n1 - 1) + window fits one LDS buffer. A piece is staged with coalesced
+// 16-byte loads (issued one piece ahead into registers) and then every output
+// of the piece adds its term. Each output thus adds harmonics in the order
+// i = 1..H of the equations. A level snapshot is taken when i is a power of two.
 // --------------------------------------------------------------------------
-template <int VAR, int DT, int WG, int R, int C>
+template <int VAR, int DT, int WG, int R, int CB>
 __global__ __launch_bounds__(WG) void k_hrms1d_fund(const Run1DParams p)
 {
     constexpr int V = Elem<DT>::kVec;
-    static_assert(C % V == 0 && kHalo % V == 0, "chunk must be a multiple of the vector");
-    constexpr int NVEC = (C + kHalo) / V;
-    constexpr int NSTAGE = ((NVEC + WG - 1) / WG) * WG * V;
+    constexpr int WIN = VAR == kFreqbin ? 0 : 1;   // 1: a window of i bins per term
+    static_assert(CB % V == 0, "chunk must be a multiple of the vector");
+    constexpr int NVEC = CB / V;
+    constexpr int VPT = (NVEC + WG - 1) / WG;
+    constexpr int BUF = VPT * WG * V;
     constexpr int T = WG * R;
-    __shared__ float lds[NSTAGE + (NSTAGE >> 5) + 1];
-    __shared__ float s_m[kMaxLevels], s_q[kMaxLevels], s_rh[kMaxLevels];
-    __shared__ int64_t s_hoff[kMaxLevels];
+    constexpr int PMAX = CB - V - kHalo;   // positions of one piece, alignment slack and window excluded
+    static_assert((WG & (WG - 1)) == 0, "WG must be a power of two");
+    constexpr int WSH = __builtin_ctz(WG);
+    __shared__ float lds[BUF + (BUF >> 5) + 1];
     __shared__ int s_item;
 
     const int tid = (int)threadIdx.x;
+    int queue = (int)(blockIdx.x % (unsigned)p.nqueues), visited = 0;
     for (;;) {
-        if (tid == 0) s_item = (int)atomicAdd(p.counter, 1u);
+        if (tid == 0) s_item = take_tile(p, queue, visited);
         __syncthreads();
-        const int item = s_item;
-        if (item >= p.ntiles) break;
+        const int item = uniform(s_item);
+        if (item < 0) break;
         const Tile tl = p.tiles[item];
-        const SpecDesc sd = p.spec[tl.spec];
-        if (tid < kMaxLevels) {
-            const LevelConst lc = p.consts[(int64_t)tl.spec * kMaxLevels + tid];
-            s_m[tid] = lc.m;
-            s_q[tid] = lc.q;
-            s_rh[tid] = lc.rh;
-            s_hoff[tid] = p.spec[tl.spec].hoff[tid];
-        }
-        const int N = sd.n;
-        const int a = tl.start;
+        const int spec = uniform(tl.spec);
+        const int a = uniform(tl.start);
+        const SpecDesc* sdp = p.spec + spec;
+        const int64_t xoff = sdp->xoff;
+        const int N = uniform(sdp->n);
+        const int nlev = uniform(sdp->nlev);
+        const LevelConst* lcon = p.consts + (int64_t)spec * kMaxLevels;
         const int aend = min(a + T, N);
         int lt = 0;
-        while (lt + 1 < sd.nlev && a < (N >> (lt + 1))) ++lt;
+        while (lt + 1 < nlev && a < (N >> (lt + 1))) ++lt;
         const int Ht = 1 << lt;
 
         float acc[R], best[R];
-        int bl[R], js[R];
+        int st[R];   // best level (bits 0..7) | Greedy offset j (bits 8..)
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             acc[r] = 0.0f;
             best[r] = 0.0f;
-            bl[r] = 0;
-            js[r] = 0;
+            st[r] = 0;
         }
 
-        int pnext = a;
+        // piece (i, n0, n1): positions i n0 .. i (n1 - 1) + WIN (i - 1)
+        auto piece_end = [&](int i, int n0) -> int {
+            return min(min(aend, N >> level_of(i)), n0 + PMAX / i);
+        };
+        auto piece_p0 = [&](int i, int n0) -> int { return align_chunk<DT>(xoff, i * n0); };
+        auto piece_vecs = [&](int i, int n1, int p0) -> int {
+            const int last = i * (n1 - 1) + WIN * (i - 1);
+            return (last + 1 - p0 + V - 1) / V;
+        };
+
+        Stage<DT, WG, VPT> stage;
+        int ci = 1, cn0 = a, cn1 = piece_end(1, a);
+        int cp0 = piece_p0(ci, cn0);
+        stage.load(p.x, xoff, N, cp0, piece_vecs(ci, cn1, cp0));
+        stage.store(lds, piece_vecs(ci, cn1, cp0));
+        __syncthreads();
         for (;;) {
-            const int p0 = align_chunk<DT>(sd.xoff, pnext);
-            stage_chunk<DT, WG, NVEC>(lds, p.x, sd.xoff, N, p0);
+            // next piece
+            int ni = ci, nn0 = cn1;
+            if (nn0 >= min(aend, N >> level_of(ni))) {
+                ni = ci + 1;
+                nn0 = a;
+            }
+            const bool more = ni <= Ht && nn0 < min(aend, N >> level_of(ni));
+            int nn1 = 0, np0 = 0, nvn = 0;
+            if (more) {
+                nn1 = piece_end(ni, nn0);
+                np0 = piece_p0(ni, nn0);
+                nvn = piece_vecs(ni, nn1, np0);
+                stage.load(p.x, xoff, N, np0, nvn);
+            }
+
+            // this piece
+            {
+                const int i = ci, n0 = cn0, n1 = cn1, p0 = cp0;
+                const int li = level_of(i);
+                const bool snap = (i & (i - 1)) == 0;
+                float m = 0.0f, q = 0.0f, rh = 0.0f;
+                int64_t ho = 0;
+                if (snap) {
+                    const LevelConst c = lcon[li];
+                    m = c.m;
+                    q = c.q;
+                    rh = c.rh;
+                    ho = sdp->hoff[li];
+                }
+                const int r0 = (n0 - a) >> WSH, r1 = (n1 - 1 - a) >> WSH;
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int b0 = a + r * WG;
-                if (b0 < aend) {
-                    const int b1 = min(b0 + WG, aend);
-                    int ilo = 1;
-                    if (p0 > 0 && b1 > 1) ilo = max(1, (p0 + b1 - 2) / (b1 - 1));
-                    int ihi = Ht;
-                    if (b0 > 0) ihi = min(Ht, (p0 + C - 1) / b0);
-                    const int n = b0 + tid;
-                    for (int i = ilo; i <= ihi; ++i) {
-                        const int li = level_of(i);
-                        const int hi = min(b1, N >> li);
-                        const int pos = n < hi ? i * n : p0 + C;
-                        if (pos >= p0 && pos < p0 + C) {
-                            const int k = pos - p0;
+                for (int r = 0; r < R; ++r) {
+                    if (r >= r0 && r <= r1) {
+                        const int n = a + (r << WSH) + tid;
+                        if (n >= n0 && n < n1) {
+                            const int k = i * n - p0;
                             float tv;
                             if constexpr (VAR == kFreqbin) {
                                 tv = lds[pidx(k)];
@@ -216,49 +318,48 @@ __global__ __launch_bounds__(WG) void k_hrms1d_fund(const Run1DParams p)
                                 if (i == 1) {
                                     tv = lds[pidx(k)];
                                 } else {
-                                    const int j = js[r];
+                                    const int j = st[r] >> 8;
                                     const float x0 = lds[pidx(k + j)];
                                     const float x1 = lds[pidx(k + j + 1)];
                                     if (x1 > x0) {
                                         tv = x1;
-                                        js[r] = j + 1;
+                                        st[r] += 256;
                                     } else {
                                         tv = x0;
                                     }
                                 }
                             }
                             acc[r] = acc[r] + tv;
-                            if ((i & (i - 1)) == 0) {
-                                const float hv = acc[r] * s_rh[li];
-                                if (p.out_mask & 1u) p.h[s_hoff[li] + n] = hv;
-                                const float snr = (hv - s_m[li]) * s_q[li];
+                            if (snap) {
+                                const float hv = acc[r] * rh;
+                                if (p.out_mask & 1u) p.h[ho + n] = hv;
+                                const float snr = (hv - m) * q;
                                 if (li == 0 || snr > best[r]) {
                                     best[r] = snr;
-                                    bl[r] = li;
+                                    st[r] = (st[r] & ~255) | li;
                                 }
                             }
                         }
                     }
                 }
             }
-            // next chunk: the lowest position >= p0 + C still needed by any harmonic
-            const int q = p0 + C;
-            int nxt = INT_MAX;
-            for (int i = 1; i <= Ht; ++i) {
-                const int hi = min(aend, N >> level_of(i));
-                if (hi <= a) continue;
-                if (i * (hi - 1) >= q) nxt = min(nxt, max(q, i * a));
-            }
-            if (nxt == INT_MAX) break;
-            pnext = nxt;
+            if (!more) break;
+            __syncthreads();   // every thread is done with this piece
+            stage.store(lds, nvn);
+            __syncthreads();
+            ci = ni;
+            cn0 = nn0;
+            cn1 = nn1;
+            cp0 = np0;
         }
 
+        const int64_t ooff = sdp->ooff;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const int n = a + r * WG + tid;
+            const int n = a + (r << WSH) + tid;
             if (n < aend) {
-                if (p.out_mask & 2u) p.max_snr[sd.ooff + n] = best[r];
-                if (p.out_mask & 4u) p.best_h[sd.ooff + n] = (uint8_t)(1u << bl[r]);
+                if (p.out_mask & 2u) p.max_snr[ooff + n] = best[r];
+                if (p.out_mask & 4u) p.best_h[ooff + n] = (uint8_t)(1u << (st[r] & 255));
             }
         }
         __syncthreads();
@@ -270,125 +371,101 @@ __global__ __launch_bounds__(WG) void k_hrms1d_fund(const Run1DParams p)
 // round(n i / H). With Lh = Hmax, term i of level H is fraction k / Lh,
 // k = i Lh / H, so every term of every level is one of the Lh bins
 // v_k = x[round(n k / Lh)], k = 1..Lh, and v_k belongs to the levels
-// H >= Lh / 2^tz(k). Bins v_k are met in increasing k, so each level still adds
-// its terms in the order i = 1..H; each level keeps its own sum.
+// H >= Lh / 2^tz(k). Bins v_k are read in increasing k, so each level still
+// adds its terms in the order i = 1..H; each level keeps its own sum.
+//
+// Neighbouring outputs read neighbouring (often equal) bins -- the stride is
+// k / Lh <= 1 -- so the loads of a wavefront are coalesced and are issued
+// straight from global memory, R outputs per thread in flight.
 // --------------------------------------------------------------------------
-template <int DT, int WG, int R, int C>
+template <int DT, int WG, int R, int CB>
 __global__ __launch_bounds__(WG) void k_hrms1d_eq1(const Run1DParams p)
 {
-    constexpr int V = Elem<DT>::kVec;
-    static_assert(C % V == 0 && kHalo % V == 0, "chunk must be a multiple of the vector");
-    constexpr int NVEC = (C + kHalo) / V;
-    constexpr int NSTAGE = ((NVEC + WG - 1) / WG) * WG * V;
     constexpr int T = WG * R;
-    __shared__ float lds[NSTAGE + (NSTAGE >> 5) + 1];
-    __shared__ float s_m[kMaxLevels], s_q[kMaxLevels], s_rh[kMaxLevels];
-    __shared__ int64_t s_hoff[kMaxLevels];
     __shared__ int s_item;
 
     const int tid = (int)threadIdx.x;
+    int queue = (int)(blockIdx.x % (unsigned)p.nqueues), visited = 0;
     for (;;) {
-        if (tid == 0) s_item = (int)atomicAdd(p.counter, 1u);
+        if (tid == 0) s_item = take_tile(p, queue, visited);
         __syncthreads();
-        const int item = s_item;
-        if (item >= p.ntiles) break;
+        const int item = uniform(s_item);
+        if (item < 0) break;
         const Tile tl = p.tiles[item];
-        const SpecDesc sd = p.spec[tl.spec];
-        if (tid < kMaxLevels) {
-            const LevelConst lc = p.consts[(int64_t)tl.spec * kMaxLevels + tid];
-            s_m[tid] = lc.m;
-            s_q[tid] = lc.q;
-            s_rh[tid] = lc.rh;
-            s_hoff[tid] = p.spec[tl.spec].hoff[tid];
-        }
-        const int N = sd.n;
-        const int a = tl.start;
+        const int spec = uniform(tl.spec);
+        const int a = uniform(tl.start);
+        const SpecDesc* sdp = p.spec + spec;
+        const int64_t xoff = sdp->xoff;
+        const int N = uniform(sdp->n);
+        const int nl = uniform(sdp->nlev);
+        const LevelConst* lcon = p.consts + (int64_t)spec * kMaxLevels;
         const int aend = min(a + T, N);
-        const int nl = sd.nlev;
         const int sh = nl - 1;
         const int Lh = 1 << sh;
         const unsigned half = (unsigned)Lh >> 1;
 
-        float acc[R][kMaxLevels], best[R];
-        int bl[R];
+        float acc[R][kMaxLevels];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
 #pragma unroll
             for (int l = 0; l < kMaxLevels; ++l) acc[r][l] = 0.0f;
-            best[r] = 0.0f;
-            bl[r] = 0;
         }
-
-        // round(n k / Lh), halves up: floor((n k + Lh/2) / Lh)
-        auto posf = [&](int n, int k) -> int {
-            return (int)(((unsigned)n * (unsigned)k + half) >> sh);
-        };
-
-        int pnext = posf(a, 1);
-        for (;;) {
-            const int p0 = align_chunk<DT>(sd.xoff, pnext);
-            stage_chunk<DT, WG, NVEC>(lds, p.x, sd.xoff, N, p0);
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int b0 = a + r * WG;
-                if (b0 < aend) {
-                    const int b1 = min(b0 + WG, aend);
-                    // pos(n, k) >= p0  <=>  n k >= p0 Lh - Lh/2
-                    int klo = 1;
-                    const int64_t tlo = (int64_t)p0 * Lh - half;
-                    if (tlo > 0 && b1 > 1) {
-                        const int64_t c = (tlo + (b1 - 1) - 1) / (b1 - 1);
-                        klo = (int)(c > Lh + 1 ? Lh + 1 : c);
-                    }
-                    // pos(n, k) < p0 + C  <=>  n k < (p0 + C) Lh - Lh/2
-                    int khi = Lh;
-                    if (b0 > 0) {
-                        const int64_t thi = ((int64_t)(p0 + C) * Lh - half - 1) / b0;
-                        khi = (int)(thi < Lh ? thi : Lh);
-                    }
-                    const int n = b0 + tid;
-                    for (int k = klo; k <= khi; ++k) {
-                        const int pos = n < b1 ? posf(n, k) : p0 + C;
-                        if (pos >= p0 && pos < p0 + C) {
-                            const float v = lds[pidx(pos - p0)];
-                            const int lmin = sh - __builtin_ctz((unsigned)k);
-#pragma unroll
-                            for (int l = 0; l < kMaxLevels; ++l) {
-                                if (l >= lmin && l < nl) acc[r][l] = acc[r][l] + v;
-                            }
-                            if (k == Lh) {
-#pragma unroll
-                                for (int l = 0; l < kMaxLevels; ++l) {
-                                    if (l < nl) {
-                                        const float hv = acc[r][l] * s_rh[l];
-                                        if (p.out_mask & 1u) p.h[s_hoff[l] + n] = hv;
-                                        const float snr = (hv - s_m[l]) * s_q[l];
-                                        if (l == 0 || snr > best[r]) {
-                                            best[r] = snr;
-                                            bl[r] = l;
-                                        }
-                                    }
-                                }
-                            }
-                        }
-                    }
-                }
-            }
-            const int q = p0 + C;
-            int nxt = INT_MAX;
-            for (int k = 1; k <= Lh; ++k) {
-                if (posf(aend - 1, k) >= q) nxt = min(nxt, max(q, posf(a, k)));
-            }
-            if (nxt == INT_MAX) break;
-            pnext = nxt;
-        }
-
+        unsigned nn[R];
+        bool act[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int n = a + r * WG + tid;
-            if (n < aend) {
-                if (p.out_mask & 2u) p.max_snr[sd.ooff + n] = best[r];
-                if (p.out_mask & 4u) p.best_h[sd.ooff + n] = (uint8_t)(1u << bl[r]);
+            act[r] = n < aend;
+            nn[r] = act[r] ? (unsigned)n : (unsigned)a;
+        }
+        for (int k = 1; k <= Lh; ++k) {
+            float v[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                // round(n k / Lh), halves up: floor((n k + Lh/2) / Lh)
+                const int pos = (int)((nn[r] * (unsigned)k + half) >> sh);
+                v[r] = load_scalar<DT>(p.x, xoff + pos);
+            }
+            const int lmin = sh - __builtin_ctz((unsigned)k);
+#pragma unroll
+            for (int l = 0; l < kMaxLevels; ++l) {
+                if (l >= lmin && l < nl) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) acc[r][l] = acc[r][l] + v[r];
+                }
+            }
+        }
+
+        const int64_t ooff = sdp->ooff;
+        float best[R];
+        int bl[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            best[r] = 0.0f;
+            bl[r] = 0;
+        }
+#pragma unroll
+        for (int l = 0; l < kMaxLevels; ++l) {
+            if (l < nl) {
+                const LevelConst c = lcon[l];
+                const int64_t ho = sdp->hoff[l];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const float hv = acc[r][l] * c.rh;
+                    if (act[r] && (p.out_mask & 1u)) p.h[ho + nn[r]] = hv;
+                    const float snr = (hv - c.m) * c.q;
+                    if (l == 0 || snr > best[r]) {
+                        best[r] = snr;
+                        bl[r] = l;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (act[r]) {
+                if (p.out_mask & 2u) p.max_snr[ooff + nn[r]] = best[r];
+                if (p.out_mask & 4u) p.best_h[ooff + nn[r]] = (uint8_t)(1u << bl[r]);
             }
         }
         __syncthreads();
@@ -487,7 +564,8 @@ __device__ void level_consts(int variant, double mu, double sigma, int H, double
 __global__ __launch_bounds__(64) void k_consts(const ConstsParams p)
 {
     const int s = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (s == 0 && p.counter) *p.counter = 0u;
+    if (s == 0 && p.counters)
+        for (int q = 0; q < kMaxQueues; ++q) p.counters[q] = 0u;
     if (s >= p.n_spec) return;
     const SpecDesc sd = p.spec[s];
     double mu, sigma;
@@ -537,47 +615,63 @@ void* eq1_kernel()
     return reinterpret_cast<void*>(&k_hrms1d_eq1<DT, WG, R, C>);
 }
 
-// Launch shapes compiled into the library.
+// Launch shapes compiled into the library: (threads, outputs per thread, LDS
+// chunk in bins) for the fundamental-indexed family and for eq. (1).
 struct ShapeEntry {
+    int eq1;   // 1: eq. (1) kernel family, 0: eq. (2)-(4)
     int wg, r, chunk;
-    void* (*fund[3][3])();   // [variant - 1][dtype]
-    void* (*eq1[3])();
+    void* (*k[3][3])();   // [variant slot][dtype]
 };
 
-template <int WG, int R, int C>
-constexpr ShapeEntry make_shape()
+template <int WG, int R, int CB>
+constexpr ShapeEntry fund_shape()
 {
-    return ShapeEntry{WG,
-                      R,
-                      C,
-                      {{&fund_kernel<kMax, kF32, WG, R, C>, &fund_kernel<kMax, kF16, WG, R, C>,
-                        &fund_kernel<kMax, kBF16, WG, R, C>},
-                       {&fund_kernel<kFreqbin, kF32, WG, R, C>,
-                        &fund_kernel<kFreqbin, kF16, WG, R, C>,
-                        &fund_kernel<kFreqbin, kBF16, WG, R, C>},
-                       {&fund_kernel<kGreedy, kF32, WG, R, C>,
-                        &fund_kernel<kGreedy, kF16, WG, R, C>,
-                        &fund_kernel<kGreedy, kBF16, WG, R, C>}},
-                      {&eq1_kernel<kF32, WG, R, C>, &eq1_kernel<kF16, WG, R, C>,
-                       &eq1_kernel<kBF16, WG, R, C>}};
+    return ShapeEntry{0, WG, R, CB,
+                      {{&fund_kernel<kMax, kF32, WG, R, CB>, &fund_kernel<kMax, kF16, WG, R, CB>,
+                        &fund_kernel<kMax, kBF16, WG, R, CB>},
+                       {&fund_kernel<kFreqbin, kF32, WG, R, CB>,
+                        &fund_kernel<kFreqbin, kF16, WG, R, CB>,
+                        &fund_kernel<kFreqbin, kBF16, WG, R, CB>},
+                       {&fund_kernel<kGreedy, kF32, WG, R, CB>,
+                        &fund_kernel<kGreedy, kF16, WG, R, CB>,
+                        &fund_kernel<kGreedy, kBF16, WG, R, CB>}}};
+}
+
+template <int WG, int R, int CB>
+constexpr ShapeEntry eq1_shape()
+{
+    return ShapeEntry{1, WG, R, CB,
+                      {{&eq1_kernel<kF32, WG, R, CB>, &eq1_kernel<kF16, WG, R, CB>,
+                        &eq1_kernel<kBF16, WG, R, CB>},
+                       {nullptr, nullptr, nullptr},
+                       {nullptr, nullptr, nullptr}}};
 }
 
 const ShapeEntry kShapes[] = {
-    make_shape<256, 16, 4096>(),
-    make_shape<256, 8, 4096>(),
+    fund_shape<256, 8, 8192>(),
+    fund_shape<256, 8, 4096>(),
+    fund_shape<256, 16, 8192>(),
+    fund_shape<512, 8, 8192>(),
+    fund_shape<128, 16, 8192>(),
+    eq1_shape<256, 8, 0>(),
+    eq1_shape<256, 4, 0>(),
+    eq1_shape<512, 8, 0>(),
 };
 
-const ShapeEntry* find_shape(const Shape1D& s)
+const ShapeEntry* find_shape(int variant, const Shape1D& s)
 {
+    const int fam = variant == kEq1 ? 1 : 0;
     for (const ShapeEntry& e : kShapes)
-        if (e.wg == s.wg && e.r == s.r && e.chunk == s.chunk) return &e;
+        if (e.eq1 == fam && e.wg == s.wg && e.r == s.r && e.chunk == s.chunk) return &e;
     return nullptr;
 }
 
-void* kernel_for(int variant, int dtype, const ShapeEntry* e)
+void* kernel_for(int variant, int dtype, const Shape1D& s)
 {
-    if (!e || dtype < 0 || dtype > 2 || variant < 0 || variant > 3) return nullptr;
-    return variant == kEq1 ? e->eq1[dtype]() : e->fund[variant - 1][dtype]();
+    if (dtype < 0 || dtype > 2 || variant < 0 || variant > 3) return nullptr;
+    const ShapeEntry* e = find_shape(variant, s);
+    if (!e) return nullptr;
+    return variant == kEq1 ? e->k[0][dtype]() : e->k[variant - 1][dtype]();
 }
 
 }  // namespace
@@ -603,12 +697,24 @@ hipError_t launch_consts(const ConstsParams& p, hipStream_t s)
 
 bool hrms1d_shape_supported(int variant, const Shape1D& shape)
 {
-    return kernel_for(variant, kF32, find_shape(shape)) != nullptr;
+    return kernel_for(variant, kF32, shape) != nullptr;
+}
+
+int hrms1d_shapes(int variant, Shape1D* out, int cap)
+{
+    const int fam = variant == kEq1 ? 1 : 0;
+    int n = 0;
+    for (const ShapeEntry& e : kShapes) {
+        if (e.eq1 != fam) continue;
+        if (out && n < cap) out[n] = Shape1D{e.wg, e.r, e.chunk};
+        ++n;
+    }
+    return n;
 }
 
 int hrms1d_max_blocks_per_cu(int variant, int dtype, const Shape1D& shape)
 {
-    void* k = kernel_for(variant, dtype, find_shape(shape));
+    void* k = kernel_for(variant, dtype, shape);
     if (!k) return 0;
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, shape.wg, 0) != hipSuccess) return 0;
@@ -618,7 +724,7 @@ int hrms1d_max_blocks_per_cu(int variant, int dtype, const Shape1D& shape)
 hipError_t launch_hrms1d(int variant, int dtype, const Shape1D& shape, const Run1DParams& p,
                          int grid, hipStream_t s)
 {
-    void* k = kernel_for(variant, dtype, find_shape(shape));
+    void* k = kernel_for(variant, dtype, shape);
     if (!k) return hipErrorInvalidValue;
     if (grid <= 0) return hipSuccess;
     Run1DParams pc = p;
