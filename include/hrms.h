@@ -126,7 +126,7 @@ typedef struct {
     int32_t stats_mode;
     int32_t reserved;         /* must be 0 */
     int64_t ld;               /* row stride in bins, >= nf */
-    const void* x;            /* device: (2 zmax + 1) rows of ld bins */
+    const void* x;            /* device: (2 zmax + 1) rows of ld bins, element-aligned */
     double* stats;            /* device: [2] = (mu, sigma) over the nf bins of every row */
     float* snr_consts;        /* device or NULL: [HRMS_MAX_LEVELS][2] */
     float* h;                 /* device: level H plane [2 zmax + 1][floor(nf / H)],

@@ -73,6 +73,27 @@ struct Plan1D {
     bool uploaded = false;
 };
 
+// A 2D plane: its rows as statistics "spectra", combined into one (mu, sigma).
+struct Plan2D {
+    int nf = 0, zmax = 0, nlev = 0;
+    int64_t ld = 0;
+    std::vector<SpecDesc> rows;
+    std::vector<Seg> segs;
+    std::vector<int32_t> seg_first;   // {0, nsegs}
+    std::vector<SpecDesc> plane;      // one descriptor: n = rows * nf
+    std::vector<int64_t> hoff;
+    DeviceBuf d_rows, d_segs, d_seg_first, d_plane, d_hoff, d_partial, d_consts;
+};
+
+// Precision form of a batch: statistics segments and fl32(1 / mu) per spectrum.
+struct PlanQ {
+    std::vector<int64_t> offsets;
+    std::vector<SpecDesc> spec;
+    std::vector<Seg> segs;
+    std::vector<int32_t> seg_first;
+    DeviceBuf d_spec, d_segs, d_seg_first, d_partial, d_inv;
+};
+
 }  // namespace
 
 struct hrms_ctx {
@@ -81,6 +102,8 @@ struct hrms_ctx {
     std::string err;
     std::string tune_path;
     std::vector<std::unique_ptr<Plan1D>> plans;   // most recent last
+    std::unique_ptr<Plan2D> plan2d;
+    std::unique_ptr<PlanQ> planq;
 };
 
 namespace {
@@ -171,14 +194,14 @@ int validate_2d(hrms_ctx* c, const hrms_run2d_args* a, bool device_ptrs)
     if (a->stats_mode != HRMS_STATS_COMPUTE && a->stats_mode != HRMS_STATS_PROVIDED)
         return fail(c, HRMS_E_INVAL, "stats_mode must be COMPUTE or PROVIDED");
     if (a->reserved != 0) return fail(c, HRMS_E_INVAL, "reserved must be 0");
+    if ((2 * (int64_t)a->zmax + 1) * (int64_t)a->nf > 0x7fffffffLL)
+        return fail(c, HRMS_E_INVAL, "(2 zmax + 1) * nf must be below 2^31");
     if (a->variant == HRMS_EQ1 || a->variant == HRMS_MAX)
         return fail(c, HRMS_E_UNSUPPORTED, "the 2D sum is implemented for FREQBIN and GREEDY");
     if (device_ptrs) {
         if (!a->x) return fail(c, HRMS_E_INVAL, "x is NULL");
-        if (reinterpret_cast<uintptr_t>(a->x) % 16)
-            return fail(c, HRMS_E_INVAL, "x must be 16-byte aligned");
-        if ((a->ld * dtype_bytes(a->dtype)) % 16)
-            return fail(c, HRMS_E_INVAL, "ld * element size must be a multiple of 16 bytes");
+        if (reinterpret_cast<uintptr_t>(a->x) % dtype_bytes(a->dtype))
+            return fail(c, HRMS_E_INVAL, "x must be aligned to its element size");
         if (!a->stats) return fail(c, HRMS_E_INVAL, "stats is NULL");
         if ((a->out_mask & HRMS_OUT_H) && !a->h)
             return fail(c, HRMS_E_INVAL, "h is NULL but HRMS_OUT_H is set");
@@ -377,6 +400,126 @@ int build_plan_1d(hrms_ctx* c, const hrms_run1d_args* a, const Shape1D& shape, P
     return HRMS_OK;
 }
 
+void build_segments(const std::vector<SpecDesc>& spec, std::vector<Seg>& segs,
+                    std::vector<int32_t>& seg_first)
+{
+    segs.clear();
+    seg_first.assign(spec.size() + 1, 0);
+    for (size_t s = 0; s < spec.size(); ++s) {
+        seg_first[s] = (int32_t)segs.size();
+        for (int64_t b = 0; b < spec[s].n; b += kStatsSeg)
+            segs.push_back(
+                Seg{(int32_t)s, (int32_t)b, (int32_t)std::min<int64_t>(kStatsSeg, spec[s].n - b), 0});
+    }
+    seg_first[spec.size()] = (int32_t)segs.size();
+}
+
+int get_plan_2d(hrms_ctx* c, const hrms_run2d_args* a, hipStream_t stream, Plan2D** out)
+{
+    const int nlev = levels_of_hmax(a->hmax);
+    Plan2D* P = c->plan2d.get();
+    if (P && P->nf == a->nf && P->zmax == a->zmax && P->ld == a->ld && P->nlev == nlev) {
+        *out = P;
+        return HRMS_OK;
+    }
+    if (P) (void)hipStreamSynchronize(stream);
+    c->plan2d.reset(new (std::nothrow) Plan2D());
+    P = c->plan2d.get();
+    if (!P) return fail(c, HRMS_E_NOMEM, "host allocation failed");
+    P->nf = a->nf;
+    P->zmax = a->zmax;
+    P->ld = a->ld;
+    P->nlev = nlev;
+    const int rows = 2 * a->zmax + 1;
+    P->rows.resize(rows);
+    for (int r = 0; r < rows; ++r) {
+        SpecDesc& d = P->rows[r];
+        d = SpecDesc{};
+        d.xoff = (int64_t)r * a->ld;
+        d.n = a->nf;
+        d.nlev = nlev;
+    }
+    build_segments(P->rows, P->segs, P->seg_first);
+    P->seg_first = {0, (int32_t)P->segs.size()};
+    SpecDesc pl{};
+    pl.n = (int32_t)((int64_t)rows * a->nf);
+    pl.nlev = nlev;
+    P->plane = {pl};
+    P->hoff.assign(kMaxLevels, -1);
+    layout_2d_into(a, P->hoff.data());
+    hipError_t e;
+    if ((e = upload(P->d_rows, P->rows, stream)) != hipSuccess) return hip_fail(c, e, "upload rows");
+    if ((e = upload(P->d_segs, P->segs, stream)) != hipSuccess) return hip_fail(c, e, "upload segs");
+    if ((e = upload(P->d_seg_first, P->seg_first, stream)) != hipSuccess)
+        return hip_fail(c, e, "upload seg_first");
+    if ((e = upload(P->d_plane, P->plane, stream)) != hipSuccess) return hip_fail(c, e, "upload plane");
+    if ((e = upload(P->d_hoff, P->hoff, stream)) != hipSuccess) return hip_fail(c, e, "upload hoff");
+    if ((e = P->d_partial.ensure(P->segs.size() * 2 * sizeof(double))) != hipSuccess)
+        return hip_fail(c, e, "alloc partials");
+    if ((e = P->d_consts.ensure(kMaxLevels * sizeof(LevelConst))) != hipSuccess)
+        return hip_fail(c, e, "alloc consts");
+    *out = P;
+    return HRMS_OK;
+}
+
+int get_plan_q(hrms_ctx* c, const hrms_quantize_args* a, hipStream_t stream, PlanQ** out)
+{
+    PlanQ* P = c->planq.get();
+    const int ns = a->n_spectra;
+    if (P && (int)P->offsets.size() == ns + 1 &&
+        std::memcmp(P->offsets.data(), a->offsets, (ns + 1) * sizeof(int64_t)) == 0) {
+        *out = P;
+        return HRMS_OK;
+    }
+    if (P) (void)hipStreamSynchronize(stream);
+    c->planq.reset(new (std::nothrow) PlanQ());
+    P = c->planq.get();
+    if (!P) return fail(c, HRMS_E_NOMEM, "host allocation failed");
+    P->offsets.assign(a->offsets, a->offsets + ns + 1);
+    P->spec.resize(ns);
+    for (int s = 0; s < ns; ++s) {
+        SpecDesc& d = P->spec[s];
+        d = SpecDesc{};
+        d.xoff = a->offsets[s];
+        d.ooff = a->offsets[s];
+        d.n = (int32_t)(a->offsets[s + 1] - a->offsets[s]);
+        d.nlev = 1;
+    }
+    build_segments(P->spec, P->segs, P->seg_first);
+    hipError_t e;
+    if ((e = upload(P->d_spec, P->spec, stream)) != hipSuccess) return hip_fail(c, e, "upload spec");
+    if ((e = upload(P->d_segs, P->segs, stream)) != hipSuccess) return hip_fail(c, e, "upload segs");
+    if ((e = upload(P->d_seg_first, P->seg_first, stream)) != hipSuccess)
+        return hip_fail(c, e, "upload seg_first");
+    if ((e = P->d_partial.ensure(P->segs.size() * 2 * sizeof(double))) != hipSuccess)
+        return hip_fail(c, e, "alloc partials");
+    if ((e = P->d_inv.ensure((size_t)ns * sizeof(float))) != hipSuccess)
+        return hip_fail(c, e, "alloc inv_mu");
+    *out = P;
+    return HRMS_OK;
+}
+
+int validate_q(hrms_ctx* c, const hrms_quantize_args* a)
+{
+    if (!a) return fail(c, HRMS_E_INVAL, "args is NULL");
+    if (a->n_spectra < 1) return fail(c, HRMS_E_INVAL, "n_spectra must be >= 1");
+    if (a->dtype != HRMS_F16 && a->dtype != HRMS_BF16)
+        return fail(c, HRMS_E_INVAL, "dtype must be HRMS_F16 or HRMS_BF16");
+    if (a->stats_mode != HRMS_STATS_COMPUTE && a->stats_mode != HRMS_STATS_PROVIDED)
+        return fail(c, HRMS_E_INVAL, "stats_mode must be COMPUTE or PROVIDED");
+    if (a->reserved != 0) return fail(c, HRMS_E_INVAL, "reserved must be 0");
+    if (!a->offsets) return fail(c, HRMS_E_INVAL, "offsets is NULL");
+    if (a->offsets[0] != 0) return fail(c, HRMS_E_INVAL, "offsets[0] must be 0");
+    for (int s = 0; s < a->n_spectra; ++s) {
+        const int64_t len = a->offsets[s + 1] - a->offsets[s];
+        if (len < 1 || len > 0x7fffffffLL)
+            return fail(c, HRMS_E_INVAL, "spectrum " + std::to_string(s) + " has an invalid length");
+    }
+    if (!a->x || !a->y || !a->stats || !a->stats_out)
+        return fail(c, HRMS_E_INVAL, "x, y, stats and stats_out must be non-NULL");
+    return HRMS_OK;
+}
+
 bool same_signature(const Plan1D& P, const hrms_run1d_args* a, const Shape1D& shape)
 {
     if (P.variant != a->variant || P.dtype != a->dtype) return false;
@@ -475,6 +618,8 @@ int hrms_destroy(hrms_handle h)
     (void)hipSetDevice(h->device);
     (void)hipDeviceSynchronize();
     h->plans.clear();
+    h->plan2d.reset();
+    h->planq.reset();
     (void)hipSetDevice(cur);
     delete h;
     return HRMS_OK;
@@ -561,20 +706,96 @@ int hrms_run_1d(hrms_handle h, const hrms_run1d_args* a, void* hip_stream)
 
 int hrms_run_2d(hrms_handle h, const hrms_run2d_args* a, void* hip_stream)
 {
-    (void)hip_stream;
     if (!h) return fail(nullptr, HRMS_E_INVAL, "handle is NULL");
     h->err.clear();
     int st = validate_2d(h, a, true);
     if (st != HRMS_OK) return st;
-    return fail(h, HRMS_E_UNSUPPORTED, "2D sum not built yet");
+    hipError_t e = hipSetDevice(h->device);
+    if (e != hipSuccess) return hip_fail(h, e, "hipSetDevice");
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    Plan2D* P = nullptr;
+    st = get_plan_2d(h, a, stream, &P);
+    if (st != HRMS_OK) return st;
+    const bool compute = a->stats_mode == HRMS_STATS_COMPUTE;
+    if (compute) {
+        StatsParams sp{a->x, (const SpecDesc*)P->d_rows.p, (const Seg*)P->d_segs.p,
+                       (double*)P->d_partial.p, (int32_t)P->segs.size()};
+        if ((e = launch_stats_partial(a->dtype, sp, stream)) != hipSuccess)
+            return hip_fail(h, e, "statistics launch");
+    }
+    ConstsParams cp{};
+    cp.spec = (const SpecDesc*)P->d_plane.p;
+    cp.segs = (const Seg*)P->d_segs.p;
+    cp.seg_first = (const int32_t*)P->d_seg_first.p;
+    cp.partial = (const double*)P->d_partial.p;
+    cp.stats = a->stats;
+    cp.consts = (LevelConst*)P->d_consts.p;
+    cp.user_consts = a->snr_consts;
+    cp.counters = nullptr;
+    cp.n_spec = 1;
+    cp.variant = a->variant;
+    cp.compute_stats = compute ? 1 : 0;
+    if ((e = launch_consts(cp, stream)) != hipSuccess) return hip_fail(h, e, "constants launch");
+    if (a->out_mask != 0) {
+        Run2DParams rp{};
+        rp.x = a->x;
+        rp.ld = a->ld;
+        rp.consts = (const LevelConst*)P->d_consts.p;
+        rp.h = a->h;
+        rp.max_snr = a->max_snr;
+        rp.best_h = a->best_h;
+        rp.hoff = (const int64_t*)P->d_hoff.p;
+        rp.nf = a->nf;
+        rp.zmax = a->zmax;
+        rp.nlev = P->nlev;
+        rp.out_mask = a->out_mask;
+        rp.zgroups = (2 * a->zmax + 1 + 3) / 4;
+        if ((e = launch_hrms2d(a->variant, a->dtype, rp, stream)) != hipSuccess)
+            return hip_fail(h, e, "2D harmonic-sum launch");
+    }
+    return HRMS_OK;
 }
 
 int hrms_quantize(hrms_handle h, const hrms_quantize_args* a, void* hip_stream)
 {
-    (void)hip_stream;
-    (void)a;
     if (!h) return fail(nullptr, HRMS_E_INVAL, "handle is NULL");
-    return fail(h, HRMS_E_UNSUPPORTED, "quantisation not built yet");
+    h->err.clear();
+    int st = validate_q(h, a);
+    if (st != HRMS_OK) return st;
+    hipError_t e = hipSetDevice(h->device);
+    if (e != hipSuccess) return hip_fail(h, e, "hipSetDevice");
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    PlanQ* P = nullptr;
+    st = get_plan_q(h, a, stream, &P);
+    if (st != HRMS_OK) return st;
+    const bool compute = a->stats_mode == HRMS_STATS_COMPUTE;
+    if (compute) {
+        StatsParams sp{a->x, (const SpecDesc*)P->d_spec.p, (const Seg*)P->d_segs.p,
+                       (double*)P->d_partial.p, (int32_t)P->segs.size()};
+        if ((e = launch_stats_partial(HRMS_F32, sp, stream)) != hipSuccess)
+            return hip_fail(h, e, "statistics launch");
+    }
+    QuantConstParams qc{};
+    qc.spec = (const SpecDesc*)P->d_spec.p;
+    qc.seg_first = (const int32_t*)P->d_seg_first.p;
+    qc.partial = (const double*)P->d_partial.p;
+    qc.stats = a->stats;
+    qc.stats_out = a->stats_out;
+    qc.inv_mu = (float*)P->d_inv.p;
+    qc.n_spec = a->n_spectra;
+    qc.compute_stats = compute ? 1 : 0;
+    if ((e = launch_quant_consts(qc, stream)) != hipSuccess)
+        return hip_fail(h, e, "normalisation constants launch");
+    QuantParams qp{};
+    qp.x = a->x;
+    qp.spec = (const SpecDesc*)P->d_spec.p;
+    qp.segs = (const Seg*)P->d_segs.p;
+    qp.inv_mu = (const float*)P->d_inv.p;
+    qp.y = a->y;
+    qp.nsegs = (int32_t)P->segs.size();
+    if ((e = launch_quantize(a->dtype, qp, stream)) != hipSuccess)
+        return hip_fail(h, e, "quantisation launch");
+    return HRMS_OK;
 }
 
 }  // extern "C"

@@ -89,22 +89,33 @@ struct Run2DParams {
     float* h;
     float* max_snr;
     uint8_t* best_h;
-    int64_t hoff[kMaxLevels];
+    const int64_t* hoff;        // [kMaxLevels] first float of each level plane
     int32_t nf;
     int32_t zmax;
     int32_t nlev;
     uint32_t out_mask;
+    int32_t zgroups;            // ceil((2 zmax + 1) / rows per workgroup)
+};
+
+// Normalisation constants of the precision form, one per spectrum.
+struct QuantConstParams {
+    const SpecDesc* spec;
+    const int32_t* seg_first;
+    const double* partial;
+    double* stats;              // raw (mu, sigma): written (compute) or read
+    double* stats_out;          // (1, sigma / mu)
+    float* inv_mu;              // fl32(1 / mu)
+    int32_t n_spec;
+    int32_t compute_stats;
 };
 
 struct QuantParams {
     const float* x;
     const SpecDesc* spec;       // xoff = first bin, n = bins
     const Seg* segs;
-    const double* stats;        // raw (mu, sigma) per spectrum
-    double* stats_out;          // (1, sigma / mu)
+    const float* inv_mu;
     void* y;
     int32_t nsegs;
-    int32_t n_spec;
 };
 
 // Launch shapes of the 1D harmonic-sum kernel family.
@@ -126,6 +137,7 @@ bool hrms1d_shape_supported(int variant, const Shape1D& shape);
 // writes up to `cap` of them.
 int hrms1d_shapes(int variant, Shape1D* out, int cap);
 hipError_t launch_hrms2d(int variant, int dtype, const Run2DParams& p, hipStream_t s);
+hipError_t launch_quant_consts(const QuantConstParams& p, hipStream_t s);
 hipError_t launch_quantize(int dtype, const QuantParams& p, hipStream_t s);
 
 }  // namespace hrms

@@ -603,6 +603,147 @@ __global__ __launch_bounds__(64) void k_consts(const ConstsParams p)
     }
 }
 
+// --------------------------------------------------------------------------
+// 2D frequency x fdot plane (freq-bin and Greedy). Output (m, z) of level H is
+// the fundamental at frequency m whose H-th harmonic has fdot z; harmonic i
+// reads row round(i z / H) (halves away from zero) at frequency i m (freq-bin)
+// or i m + j (Greedy, j as in eq. (4)). Each level is summed on its own, in
+// the order i = 1..H. A thread owns one output; a workgroup holds 64
+// consecutive frequencies of kZRows fdot rows, the rows being the fastest grid
+// dimension so that neighbouring workgroups read the same columns.
+// --------------------------------------------------------------------------
+constexpr int kZRows = 4;
+
+__device__ __forceinline__ int row_of(int iz, int l)
+{
+    // round(iz / 2^l), halves away from zero
+    const int H = 1 << l;
+    return iz >= 0 ? (2 * iz + H) >> (l + 1) : -((-2 * iz + H) >> (l + 1));
+}
+
+template <int VAR, int DT>
+__global__ __launch_bounds__(64 * kZRows) void k_hrms2d(const Run2DParams p)
+{
+    const int lane = (int)threadIdx.x & 63;
+    const int zl = (int)threadIdx.x >> 6;
+    const int zg = (int)(blockIdx.x % (unsigned)p.zgroups);
+    const int mb = (int)(blockIdx.x / (unsigned)p.zgroups);
+    const int rows = 2 * p.zmax + 1;
+    const int r = zg * kZRows + zl;
+    const int m = mb * 64 + lane;
+    if (r >= rows || m >= p.nf) return;
+    const int z = r - p.zmax;
+    const int64_t ld = p.ld;
+    float best = 0.0f;
+    int bl = 0;
+#pragma unroll
+    for (int l = 0; l < kMaxLevels; ++l) {
+        if (l < p.nlev && m < (p.nf >> l)) {
+            const int H = 1 << l;
+            float acc;
+            if constexpr (VAR == kFreqbin) {
+                acc = 0.0f;
+#pragma unroll
+                for (int i = 1; i <= (1 << (kMaxLevels - 1)); ++i) {
+                    if (i <= H) {
+                        const int row = row_of(i * z, l) + p.zmax;
+                        acc = acc + load_scalar<DT>(p.x, (int64_t)row * ld + (int64_t)i * m);
+                    }
+                }
+            } else {
+                const int row1 = row_of(z, l) + p.zmax;
+                acc = load_scalar<DT>(p.x, (int64_t)row1 * ld + m);
+                int j = 0;
+#pragma unroll
+                for (int k = 2; k <= (1 << (kMaxLevels - 1)); ++k) {
+                    if (k <= H) {
+                        const int row = row_of(k * z, l) + p.zmax;
+                        const int64_t base = (int64_t)row * ld + (int64_t)k * m + j;
+                        const float x0 = load_scalar<DT>(p.x, base);
+                        const float x1 = load_scalar<DT>(p.x, base + 1);
+                        if (x1 > x0) {
+                            acc = acc + x1;
+                            j += 1;
+                        } else {
+                            acc = acc + x0;
+                        }
+                    }
+                }
+            }
+            const LevelConst c = p.consts[l];
+            const float hv = acc * c.rh;
+            if (p.out_mask & 1u) p.h[p.hoff[l] + (int64_t)r * (p.nf >> l) + m] = hv;
+            const float snr = (hv - c.m) * c.q;
+            if (l == 0 || snr > best) {
+                best = snr;
+                bl = l;
+            }
+        }
+    }
+    const int64_t o = (int64_t)r * p.nf + m;
+    if (p.out_mask & 2u) p.max_snr[o] = best;
+    if (p.out_mask & 4u) p.best_h[o] = (uint8_t)(1u << bl);
+}
+
+// --------------------------------------------------------------------------
+// Precision form: y = round_to_dtype(x * fl32(1 / mu)), round to nearest
+// even; FP16 saturates at +-65504.
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_quant_consts(const QuantConstParams p)
+{
+    const int s = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (s >= p.n_spec) return;
+    double mu, sigma;
+    if (p.compute_stats) {
+        double t1 = 0.0, t2 = 0.0;
+        for (int g = p.seg_first[s]; g < p.seg_first[s + 1]; ++g) {
+            t1 = t1 + p.partial[2 * (int64_t)g];
+            t2 = t2 + p.partial[2 * (int64_t)g + 1];
+        }
+        const double nb = (double)p.spec[s].n;
+        mu = t1 / nb;
+        double var = t2 / nb - mu * mu;
+        if (var < 0.0) var = 0.0;
+        sigma = sqrt(var);
+        p.stats[2 * (int64_t)s] = mu;
+        p.stats[2 * (int64_t)s + 1] = sigma;
+    } else {
+        mu = p.stats[2 * (int64_t)s];
+        sigma = p.stats[2 * (int64_t)s + 1];
+    }
+    p.stats_out[2 * (int64_t)s] = 1.0;
+    p.stats_out[2 * (int64_t)s + 1] = sigma / mu;
+    p.inv_mu[s] = (float)(1.0 / mu);
+}
+
+__device__ __forceinline__ uint16_t to_f16_sat(float v)
+{
+    if (v > 65504.0f) v = 65504.0f;
+    if (v < -65504.0f) v = -65504.0f;
+    return __builtin_bit_cast(uint16_t, (_Float16)v);
+}
+
+__device__ __forceinline__ uint16_t to_bf16_rne(float v)
+{
+    const uint32_t u = __float_as_uint(v);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x0040u);   // quiet NaN
+    return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+template <int DT>
+__global__ __launch_bounds__(kStatsWG) void k_quantize(const QuantParams p)
+{
+    const Seg sg = p.segs[blockIdx.x];
+    const SpecDesc sd = p.spec[sg.spec];
+    const float inv = p.inv_mu[sg.spec];
+    uint16_t* y = static_cast<uint16_t*>(p.y);
+    const int64_t base = sd.xoff + sg.start;
+    for (int e = (int)threadIdx.x; e < sg.len; e += kStatsWG) {
+        const float v = p.x[base + e] * inv;
+        y[base + e] = DT == kF16 ? to_f16_sat(v) : to_bf16_rne(v);
+    }
+}
+
 template <int VAR, int DT, int WG, int R, int C>
 void* fund_kernel()
 {
@@ -732,8 +873,45 @@ hipError_t launch_hrms1d(int variant, int dtype, const Shape1D& shape, const Run
     return hipLaunchKernel(k, dim3(grid), dim3(shape.wg), args, 0, s);
 }
 
-hipError_t launch_hrms2d(int, int, const Run2DParams&, hipStream_t) { return hipErrorNotSupported; }
+hipError_t launch_hrms2d(int variant, int dtype, const Run2DParams& p, hipStream_t s)
+{
+    const int64_t mblocks = ((int64_t)p.nf + 63) / 64;
+    const int64_t blocks = mblocks * p.zgroups;
+    if (blocks <= 0) return hipSuccess;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    dim3 grid((unsigned)blocks), block(64 * kZRows);
+    if (variant == kFreqbin) {
+        switch (dtype) {
+        case kF32: hipLaunchKernelGGL((k_hrms2d<kFreqbin, kF32>), grid, block, 0, s, p); break;
+        case kF16: hipLaunchKernelGGL((k_hrms2d<kFreqbin, kF16>), grid, block, 0, s, p); break;
+        default: hipLaunchKernelGGL((k_hrms2d<kFreqbin, kBF16>), grid, block, 0, s, p); break;
+        }
+    } else if (variant == kGreedy) {
+        switch (dtype) {
+        case kF32: hipLaunchKernelGGL((k_hrms2d<kGreedy, kF32>), grid, block, 0, s, p); break;
+        case kF16: hipLaunchKernelGGL((k_hrms2d<kGreedy, kF16>), grid, block, 0, s, p); break;
+        default: hipLaunchKernelGGL((k_hrms2d<kGreedy, kBF16>), grid, block, 0, s, p); break;
+        }
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
 
-hipError_t launch_quantize(int, const QuantParams&, hipStream_t) { return hipErrorNotSupported; }
+hipError_t launch_quant_consts(const QuantConstParams& p, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_quant_consts, dim3((p.n_spec + 63) / 64), dim3(64), 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_quantize(int dtype, const QuantParams& p, hipStream_t s)
+{
+    if (p.nsegs <= 0) return hipSuccess;
+    if (dtype == kF16)
+        hipLaunchKernelGGL(k_quantize<kF16>, dim3(p.nsegs), dim3(kStatsWG), 0, s, p);
+    else
+        hipLaunchKernelGGL(k_quantize<kBF16>, dim3(p.nsegs), dim3(kStatsWG), 0, s, p);
+    return hipGetLastError();
+}
 
 }  // namespace hrms

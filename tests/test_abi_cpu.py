@@ -150,7 +150,7 @@ def test_layout_2d_and_unsupported_variants():
         assert H.lib().hrms_layout_2d(C.byref(a), None, None) == H.HRMS_E_UNSUPPORTED
     a.variant = H.HRMS_GREEDY
     a.ld = 999
-    assert H.lib().hrms_layout_2d(C.byref(a), None, None) == H.HRMS_E_INVAL
+    assert H.lib().hrms_layout_2d(C.byref(a), None, None) == H.HRMS_E_INVAL   # ld < nf
     a.ld = 1000
     a.reserved = 1
     assert H.lib().hrms_layout_2d(C.byref(a), None, None) == H.HRMS_E_INVAL
