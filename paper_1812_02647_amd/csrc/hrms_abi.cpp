@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <new>
 #include <string>
@@ -19,6 +20,7 @@
 
 #include "../../include/hrms.h"
 #include "hrms_internal.h"
+#include "hrms_plan.h"
 
 using namespace hrms;
 
@@ -62,14 +64,16 @@ struct Plan1D {
     Shape1D shape{};
     // host mirrors (kept alive for the asynchronous uploads)
     std::vector<SpecDesc> spec;
-    std::vector<Tile> tiles;
+    std::vector<TileRec> tiles;
+    std::vector<PieceRec> pieces;
     std::vector<int32_t> qbeg;
     std::vector<Seg> segs;
     std::vector<int32_t> seg_first;
     int grid = 0;
     int nqueues = 1;
     // device
-    DeviceBuf d_spec, d_tiles, d_qbeg, d_segs, d_seg_first, d_partial, d_consts, d_counter;
+    DeviceBuf d_spec, d_tiles, d_pieces, d_qbeg, d_segs, d_seg_first, d_partial, d_consts,
+        d_counter;
     bool uploaded = false;
 };
 
@@ -263,31 +267,6 @@ Shape1D default_shape(int variant)
     return Shape1D{256, 8, 8192};
 }
 
-// Bins a tile stages: harmonic spans, counted once where they overlap.
-int64_t tile_cost(int variant, int64_t n, int nlev, int64_t a, int64_t t)
-{
-    const int64_t aend = std::min(a + t, n);
-    if (variant == HRMS_EQ1) {
-        const int64_t lh = (int64_t)1 << (nlev - 1);
-        return (aend - a) * (lh + 1) / 2 + lh;
-    }
-    int lt = 0;
-    while (lt + 1 < nlev && a < (n >> (lt + 1))) ++lt;
-    const int ht = 1 << lt;
-    int64_t cost = 0, covered = 0;
-    for (int i = 1; i <= ht; ++i) {
-        int li = 0;
-        while ((1 << li) < i) ++li;
-        const int64_t hi = std::min(aend, n >> li);
-        if (hi <= a) continue;
-        const int64_t lo_p = i * a, hi_p = i * (hi - 1) + i;
-        const int64_t start = std::max(lo_p, covered);
-        if (hi_p > start) cost += hi_p - start;
-        covered = std::max(covered, hi_p);
-    }
-    return cost;
-}
-
 template <typename T>
 hipError_t upload(DeviceBuf& b, const std::vector<T>& v, hipStream_t s)
 {
@@ -323,23 +302,62 @@ int build_plan_1d(hrms_ctx* c, const hrms_run1d_args* a, const Shape1D& shape, P
     // Tiles. Spectra are spread over one queue per XCD, balancing their total
     // cost; a queue lists its spectra one after the other (so the bins of a
     // spectrum stay in that XCD's L2 while its tiles run), each spectrum's
-    // tiles most expensive first.
-    const int64_t T = (int64_t)shape.wg * shape.r;
+    // tiles most expensive first. Piece lists depend only on (length, levels,
+    // alignment) and are shared by the spectra that agree on them.
+    const int T = shape.wg * shape.r;
+    const int vec = 16 / dtype_bytes(a->dtype);
     const int nq = (c->cu_count >= kMaxQueues && c->cu_count % kMaxQueues == 0) ? kMaxQueues : 1;
-    std::vector<std::vector<std::pair<int64_t, Tile>>> per_spec(ns);
+    struct Geo {
+        int n, nlev, xmod;
+        bool operator<(const Geo& o) const
+        {
+            return n != o.n ? n < o.n : nlev != o.nlev ? nlev < o.nlev : xmod < o.xmod;
+        }
+    };
+    struct TileSched {
+        int32_t pbeg, pcount;
+        int64_t cost;
+    };
+    std::map<Geo, std::vector<TileSched>> sched;
+    P->pieces.clear();
+    std::vector<std::vector<std::pair<int64_t, TileRec>>> per_spec(ns);
     std::vector<std::pair<int64_t, int>> spec_cost(ns);
     for (int s = 0; s < ns; ++s) {
-        const int64_t n = P->spec[s].n;
+        const int n = P->spec[s].n;
+        const Geo g{n, (int)P->nlev[s], (int)(a->offsets[s] % vec)};
+        auto it = sched.find(g);
+        if (it == sched.end()) {
+            std::vector<TileSched> ts;
+            for (int t0 = 0; t0 < n; t0 += T) {
+                TileSched x{(int32_t)P->pieces.size(), 0, 0};
+                if (a->variant == HRMS_EQ1) {
+                    x.cost = (int64_t)std::min(T, n - t0) * ((1 << (g.nlev - 1)) + 1);
+                } else {
+                    x.cost = tile_pieces(a->variant, vec, shape.chunk, n, g.nlev, g.xmod, t0, T,
+                                         &P->pieces);
+                    x.pcount = (int32_t)P->pieces.size() - x.pbeg;
+                }
+                ts.push_back(x);
+            }
+            it = sched.emplace(g, std::move(ts)).first;
+        }
         int64_t tot = 0;
-        for (int64_t t0 = 0; t0 < n; t0 += T) {
-            const int64_t cst = tile_cost(a->variant, n, P->nlev[s], t0, T);
-            per_spec[s].push_back({cst, Tile{s, (int32_t)t0}});
-            tot += cst;
+        for (size_t k = 0; k < it->second.size(); ++k) {
+            const TileSched& x = it->second[k];
+            TileRec tr;
+            tr.xoff = a->offsets[s];
+            tr.n = n;
+            tr.a = (int32_t)(k * (size_t)T);
+            tr.pbeg = x.pbeg;
+            tr.pcount = x.pcount;
+            tr.spec = s;
+            tr.nlev = g.nlev;
+            per_spec[s].push_back({x.cost, tr});
+            tot += x.cost;
         }
         std::stable_sort(per_spec[s].begin(), per_spec[s].end(),
-                         [](const std::pair<int64_t, Tile>& x, const std::pair<int64_t, Tile>& y) {
-                             return x.first > y.first;
-                         });
+                         [](const std::pair<int64_t, TileRec>& x,
+                            const std::pair<int64_t, TileRec>& y) { return x.first > y.first; });
         spec_cost[s] = {tot, s};
     }
     std::stable_sort(spec_cost.begin(), spec_cost.end(),
@@ -364,6 +382,7 @@ int build_plan_1d(hrms_ctx* c, const hrms_run1d_args* a, const Shape1D& shape, P
     }
     P->qbeg[nq] = (int32_t)P->tiles.size();
     P->nqueues = nq;
+    if (P->pieces.empty()) P->pieces.push_back(PieceRec{0, 0, 0, 0});
 
     // statistics segments
     P->segs.clear();
@@ -378,8 +397,9 @@ int build_plan_1d(hrms_ctx* c, const hrms_run1d_args* a, const Shape1D& shape, P
 
     const int per_cu = hrms1d_max_blocks_per_cu(a->variant, a->dtype, shape);
     if (per_cu <= 0) return fail(c, HRMS_E_HIP, "occupancy query failed for the 1D kernel");
-    int64_t grid = std::min<int64_t>((int64_t)P->tiles.size(), (int64_t)c->cu_count * per_cu);
-    if (grid >= nq) grid -= grid % nq;   // every queue gets the same number of workgroups
+    // one resident wave of workgroups, the same number per queue
+    int64_t grid = std::min<int64_t>((int64_t)c->cu_count * per_cu, (int64_t)P->tiles.size());
+    if (grid >= nq) grid -= grid % nq;
     P->grid = (int)std::max<int64_t>(grid, 1);
 
     hipError_t e;
@@ -387,6 +407,8 @@ int build_plan_1d(hrms_ctx* c, const hrms_run1d_args* a, const Shape1D& shape, P
     if ((e = upload(P->d_tiles, P->tiles, stream)) != hipSuccess)
         return hip_fail(c, e, "upload tiles");
     if ((e = upload(P->d_qbeg, P->qbeg, stream)) != hipSuccess) return hip_fail(c, e, "upload qbeg");
+    if ((e = upload(P->d_pieces, P->pieces, stream)) != hipSuccess)
+        return hip_fail(c, e, "upload pieces");
     if ((e = upload(P->d_segs, P->segs, stream)) != hipSuccess) return hip_fail(c, e, "upload segs");
     if ((e = upload(P->d_seg_first, P->seg_first, stream)) != hipSuccess)
         return hip_fail(c, e, "upload seg_first");
@@ -395,7 +417,7 @@ int build_plan_1d(hrms_ctx* c, const hrms_run1d_args* a, const Shape1D& shape, P
     if ((e = P->d_consts.ensure((size_t)ns * kMaxLevels * sizeof(LevelConst))) != hipSuccess)
         return hip_fail(c, e, "alloc consts");
     if ((e = P->d_counter.ensure(sizeof(unsigned int) * kMaxQueues)) != hipSuccess)
-        return hip_fail(c, e, "alloc counter");
+        return hip_fail(c, e, "alloc counters");
     P->uploaded = true;
     return HRMS_OK;
 }
@@ -689,13 +711,14 @@ int hrms_run_1d(hrms_handle h, const hrms_run1d_args* a, void* hip_stream)
         Run1DParams rp{};
         rp.x = a->x;
         rp.spec = (const SpecDesc*)P->d_spec.p;
-        rp.tiles = (const Tile*)P->d_tiles.p;
+        rp.tiles = (const TileRec*)P->d_tiles.p;
+        rp.pieces = (const PieceRec*)P->d_pieces.p;
         rp.consts = (const LevelConst*)P->d_consts.p;
         rp.h = a->h;
         rp.max_snr = a->max_snr;
         rp.best_h = a->best_h;
-        rp.counters = (unsigned int*)P->d_counter.p;
         rp.qbeg = (const int32_t*)P->d_qbeg.p;
+        rp.counters = (unsigned int*)P->d_counter.p;
         rp.nqueues = P->nqueues;
         rp.out_mask = a->out_mask;
         if ((e = launch_hrms1d(a->variant, a->dtype, shape, rp, P->grid, stream)) != hipSuccess)

@@ -6,32 +6,9 @@
 
 #include <cstdint>
 
+#include "hrms_types.h"
+
 namespace hrms {
-
-constexpr int kMaxLevels = 6;
-
-// One spectrum of a 1D batch (or one row group of a plane), as the kernels see it.
-struct SpecDesc {
-    int64_t xoff;               // first input bin in x (elements)
-    int64_t ooff;               // first bin of max_snr / best_h
-    int64_t hoff[kMaxLevels];   // first float of each level plane in h, -1 if absent
-    int32_t n;                  // bins
-    int32_t nlev;               // levels: log2(Hmax) + 1
-};
-
-// A tile of consecutive outputs [start, start + T) of one spectrum.
-struct Tile {
-    int32_t spec;
-    int32_t start;
-};
-
-// A segment of one spectrum for the statistics reduction.
-struct Seg {
-    int32_t spec;
-    int32_t start;
-    int32_t len;
-    int32_t pad;
-};
 
 // Per-level constants of one spectrum: null mean, inverse null spread and the
 // level's scale fl32(1 / sqrt(H)).
@@ -42,20 +19,22 @@ struct LevelConst {
     float pad;
 };
 
-// Work queues of the persistent grid: one per XCD (workgroup w starts on queue
-// w % nqueues and moves on to the next queue when its own is drained).
+// Work queues of the persistent grid: one per XCD. Workgroup w starts on
+// queue w % nqueues, claims its tiles through the queue's atomic counter and
+// moves on to the following queues once its own is drained.
 constexpr int kMaxQueues = 8;
 
 struct Run1DParams {
     const void* x;
     const SpecDesc* spec;
-    const Tile* tiles;          // queue q holds tiles[qbeg[q] .. qbeg[q + 1])
+    const TileRec* tiles;       // queue q holds tiles[qbeg[q] .. qbeg[q + 1])
+    const PieceRec* pieces;
     const LevelConst* consts;   // [n_spec][kMaxLevels]
     float* h;
     float* max_snr;
     uint8_t* best_h;
-    unsigned int* counters;     // [kMaxQueues] tiles taken from each queue
     const int32_t* qbeg;        // [nqueues + 1]
+    unsigned int* counters;     // [kMaxQueues] tiles claimed from each queue
     int32_t nqueues;
     uint32_t out_mask;
 };
@@ -76,7 +55,7 @@ struct ConstsParams {
     double* stats;              // [n_spec][2]
     LevelConst* consts;         // [n_spec][kMaxLevels]
     float* user_consts;         // optional [n_spec][kMaxLevels][2]
-    unsigned int* counters;     // [kMaxQueues], reset to 0 for the following launch
+    unsigned int* counters;     // [kMaxQueues] reset to 0 for the following launch, or NULL
     int32_t n_spec;
     int32_t variant;
     int32_t compute_stats;      // 1: reduce partials into stats; 0: read stats

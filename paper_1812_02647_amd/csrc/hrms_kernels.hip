@@ -178,9 +178,10 @@ struct Stage {
     }
 };
 
-// Takes the next tile for this workgroup (thread 0 only): from the current
-// queue while it lasts, then from the following queues in turn.
-__device__ __forceinline__ int take_tile(const Run1DParams& p, int& q, int& visited)
+// Claims the next tile of this workgroup (call from one thread): from the
+// current queue while it lasts, then from the following queues in turn;
+// -1 once every queue is drained.
+__device__ __forceinline__ int claim_tile(const Run1DParams& p, int& q, int& visited)
 {
     while (visited < p.nqueues) {
         const unsigned k = atomicAdd(&p.counters[q], 1u);
@@ -196,173 +197,176 @@ __device__ __forceinline__ int take_tile(const Run1DParams& p, int& q, int& visi
 // eq. (2)-(4): outputs indexed by the fundamental.
 //
 // A tile is the T = WG * R outputs [a, aend) of one spectrum; thread t holds
-// outputs a + r WG + t (r < R) in registers. Harmonic i is needed for the
-// outputs n < hi_i = min(aend, floor(N / 2^level(i))) and reads positions i n
-// (+ up to i - 1 bins of window for eq. (2) and (4)).
+// outputs a + r WG + t (r < R) in registers: running sum, best SNR, best level
+// and Greedy's offset j. Harmonic i is needed for the outputs
+// n < floor(N / 2^level(i)) and reads positions i n (+ up to i - 1 bins of
+// window for eq. (2) and (4)).
 //
-// The tile walks harmonic-major: for i = 1..Ht, its valid outputs are cut into
-// pieces [n0, n1) of at most PMAX / i outputs, so that the span i n0 ..
-// i (n1 - 1) + window fits one LDS buffer. A piece is staged with coalesced
-// 16-byte loads (issued one piece ahead into registers) and then every output
-// of the piece adds its term. Each output thus adds harmonics in the order
-// i = 1..H of the equations. A level snapshot is taken when i is a power of two.
+// The tile walks harmonic-major through a list of pieces built on the host:
+// piece (i, [n0, n1)) stages the bins i n0 .. i (n1 - 1) + window, which fit
+// one LDS buffer, and every output of the piece then adds its term. Each
+// output thus adds its harmonics in the order i = 1..H of the equations; a
+// level snapshot is taken when i is a power of two.
+//
+// Workgroup w serves the tiles of queue q = w % nq with stride G = grid / nq.
+// The next piece -- of this tile or of the next one -- is loaded into
+// registers while the current one is computed.
 // --------------------------------------------------------------------------
 template <int VAR, int DT, int WG, int R, int CB>
 __global__ __launch_bounds__(WG) void k_hrms1d_fund(const Run1DParams p)
 {
     constexpr int V = Elem<DT>::kVec;
-    constexpr int WIN = VAR == kFreqbin ? 0 : 1;   // 1: a window of i bins per term
     static_assert(CB % V == 0, "chunk must be a multiple of the vector");
     constexpr int NVEC = CB / V;
     constexpr int VPT = (NVEC + WG - 1) / WG;
     constexpr int BUF = VPT * WG * V;
     constexpr int T = WG * R;
-    constexpr int PMAX = CB - V - kHalo;   // positions of one piece, alignment slack and window excluded
     static_assert((WG & (WG - 1)) == 0, "WG must be a power of two");
+    static_assert(T <= 0xffff, "tile offsets are 16-bit");
     constexpr int WSH = __builtin_ctz(WG);
     __shared__ float lds[BUF + (BUF >> 5) + 1];
-    __shared__ int s_item;
 
     const int tid = (int)threadIdx.x;
-    int queue = (int)(blockIdx.x % (unsigned)p.nqueues), visited = 0;
-    for (;;) {
-        if (tid == 0) s_item = take_tile(p, queue, visited);
-        __syncthreads();
-        const int item = uniform(s_item);
-        if (item < 0) break;
-        const Tile tl = p.tiles[item];
-        const int spec = uniform(tl.spec);
-        const int a = uniform(tl.start);
-        const SpecDesc* sdp = p.spec + spec;
-        const int64_t xoff = sdp->xoff;
-        const int N = uniform(sdp->n);
-        const int nlev = uniform(sdp->nlev);
-        const LevelConst* lcon = p.consts + (int64_t)spec * kMaxLevels;
-        const int aend = min(a + T, N);
-        int lt = 0;
-        while (lt + 1 < nlev && a < (N >> (lt + 1))) ++lt;
-        const int Ht = 1 << lt;
+    // Tile claims run two tiles ahead of use: s_claim[c & 1] is written when
+    // tile c - 1 starts and read when tile c starts.
+    __shared__ int s_claim[3];
+    int cq = (int)(blockIdx.x % (unsigned)p.nqueues), visited = 0;
+    if (tid == 0) {
+        s_claim[2] = claim_tile(p, cq, visited);   // tile 0
+        s_claim[1] = claim_tile(p, cq, visited);   // tile 1
+        s_claim[0] = claim_tile(p, cq, visited);   // tile 2
+    }
+    __syncthreads();
+    int t = uniform(s_claim[2]);
+    if (t < 0) return;
+    int tn = uniform(s_claim[1]);
+    int c = 1;   // index of the tile that tn names
 
-        float acc[R], best[R];
-        int st[R];   // best level (bits 0..7) | Greedy offset j (bits 8..)
+    TileRec ct = p.tiles[t];
+    int pi = ct.pbeg, pe = ct.pbeg + ct.pcount;
+    PieceRec cp = p.pieces[pi];
+    TileRec ft = ct;   // record of tile tn, fetched a whole tile ahead of its use
+    if (tn >= 0) ft = p.tiles[tn];
+
+    float acc[R], best[R];
+    int st[R];   // best level (bits 0..7) | Greedy offset j (bits 8..)
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            acc[r] = 0.0f;
-            best[r] = 0.0f;
-            st[r] = 0;
+    for (int r = 0; r < R; ++r) {
+        acc[r] = 0.0f;
+        best[r] = 0.0f;
+        st[r] = 0;
+    }
+
+    Stage<DT, WG, VPT> stage;
+    stage.load(p.x, ct.xoff, ct.n, cp.p0, cp.nv);
+    stage.store(lds, cp.nv);
+    __syncthreads();
+    for (;;) {
+        // next piece: of this tile, else the first of the following tile
+        const bool newtile = pi + 1 >= pe;
+        const bool more = !newtile || tn >= 0;
+        const TileRec& nt = newtile ? ft : ct;
+        PieceRec np = cp;
+        if (more) {
+            np = p.pieces[newtile ? nt.pbeg : pi + 1];
+            stage.load(p.x, nt.xoff, nt.n, np.p0, np.nv);
         }
 
-        // piece (i, n0, n1): positions i n0 .. i (n1 - 1) + WIN (i - 1)
-        auto piece_end = [&](int i, int n0) -> int {
-            return min(min(aend, N >> level_of(i)), n0 + PMAX / i);
-        };
-        auto piece_p0 = [&](int i, int n0) -> int { return align_chunk<DT>(xoff, i * n0); };
-        auto piece_vecs = [&](int i, int n1, int p0) -> int {
-            const int last = i * (n1 - 1) + WIN * (i - 1);
-            return (last + 1 - p0 + V - 1) / V;
-        };
-
-        Stage<DT, WG, VPT> stage;
-        int ci = 1, cn0 = a, cn1 = piece_end(1, a);
-        int cp0 = piece_p0(ci, cn0);
-        stage.load(p.x, xoff, N, cp0, piece_vecs(ci, cn1, cp0));
-        stage.store(lds, piece_vecs(ci, cn1, cp0));
-        __syncthreads();
-        for (;;) {
-            // next piece
-            int ni = ci, nn0 = cn1;
-            if (nn0 >= min(aend, N >> level_of(ni))) {
-                ni = ci + 1;
-                nn0 = a;
+        // this piece
+        {
+            const int a = ct.a;
+            const int i = cp.ih & 0xff;
+            const int li = (cp.ih >> 8) & 0xff;
+            const bool snap = (cp.ih >> 16) & 1;
+            const int n0 = a + (cp.nr & 0xffff), n1 = a + (cp.nr >> 16);
+            const int p0 = cp.p0;
+            float m = 0.0f, qq = 0.0f, rh = 0.0f;
+            int64_t ho = 0;
+            if (snap) {
+                const LevelConst c = p.consts[(int64_t)ct.spec * kMaxLevels + li];
+                m = c.m;
+                qq = c.q;
+                rh = c.rh;
+                ho = p.spec[ct.spec].hoff[li];
             }
-            const bool more = ni <= Ht && nn0 < min(aend, N >> level_of(ni));
-            int nn1 = 0, np0 = 0, nvn = 0;
-            if (more) {
-                nn1 = piece_end(ni, nn0);
-                np0 = piece_p0(ni, nn0);
-                nvn = piece_vecs(ni, nn1, np0);
-                stage.load(p.x, xoff, N, np0, nvn);
-            }
-
-            // this piece
-            {
-                const int i = ci, n0 = cn0, n1 = cn1, p0 = cp0;
-                const int li = level_of(i);
-                const bool snap = (i & (i - 1)) == 0;
-                float m = 0.0f, q = 0.0f, rh = 0.0f;
-                int64_t ho = 0;
-                if (snap) {
-                    const LevelConst c = lcon[li];
-                    m = c.m;
-                    q = c.q;
-                    rh = c.rh;
-                    ho = sdp->hoff[li];
-                }
-                const int r0 = (n0 - a) >> WSH, r1 = (n1 - 1 - a) >> WSH;
+            const int r0 = (n0 - a) >> WSH, r1 = (n1 - 1 - a) >> WSH;
 #pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    if (r >= r0 && r <= r1) {
-                        const int n = a + (r << WSH) + tid;
-                        if (n >= n0 && n < n1) {
-                            const int k = i * n - p0;
-                            float tv;
-                            if constexpr (VAR == kFreqbin) {
+            for (int r = 0; r < R; ++r) {
+                if (r >= r0 && r <= r1) {
+                    const int n = a + (r << WSH) + tid;
+                    if (n >= n0 && n < n1) {
+                        const int k = i * n - p0;
+                        float tv;
+                        if constexpr (VAR == kFreqbin) {
+                            tv = lds[pidx(k)];
+                        } else if constexpr (VAR == kMax) {
+                            tv = lds[pidx(k)];
+                            for (int jj = 1; jj < i; ++jj) {
+                                const float w = lds[pidx(k + jj)];
+                                tv = w > tv ? w : tv;
+                            }
+                        } else {
+                            if (i == 1) {
                                 tv = lds[pidx(k)];
-                            } else if constexpr (VAR == kMax) {
-                                tv = lds[pidx(k)];
-                                for (int jj = 1; jj < i; ++jj) {
-                                    const float w = lds[pidx(k + jj)];
-                                    tv = w > tv ? w : tv;
-                                }
                             } else {
-                                if (i == 1) {
-                                    tv = lds[pidx(k)];
+                                const int j = st[r] >> 8;
+                                const float x0 = lds[pidx(k + j)];
+                                const float x1 = lds[pidx(k + j + 1)];
+                                if (x1 > x0) {
+                                    tv = x1;
+                                    st[r] += 256;
                                 } else {
-                                    const int j = st[r] >> 8;
-                                    const float x0 = lds[pidx(k + j)];
-                                    const float x1 = lds[pidx(k + j + 1)];
-                                    if (x1 > x0) {
-                                        tv = x1;
-                                        st[r] += 256;
-                                    } else {
-                                        tv = x0;
-                                    }
+                                    tv = x0;
                                 }
                             }
-                            acc[r] = acc[r] + tv;
-                            if (snap) {
-                                const float hv = acc[r] * rh;
-                                if (p.out_mask & 1u) p.h[ho + n] = hv;
-                                const float snr = (hv - m) * q;
-                                if (li == 0 || snr > best[r]) {
-                                    best[r] = snr;
-                                    st[r] = (st[r] & ~255) | li;
-                                }
+                        }
+                        acc[r] = acc[r] + tv;
+                        if (snap) {
+                            const float hv = acc[r] * rh;
+                            if (p.out_mask & 1u) p.h[ho + n] = hv;
+                            const float snr = (hv - m) * qq;
+                            if (li == 0 || snr > best[r]) {
+                                best[r] = snr;
+                                st[r] = (st[r] & ~255) | li;
                             }
                         }
                     }
                 }
             }
-            if (!more) break;
-            __syncthreads();   // every thread is done with this piece
-            stage.store(lds, nvn);
-            __syncthreads();
-            ci = ni;
-            cn0 = nn0;
-            cn1 = nn1;
-            cp0 = np0;
         }
 
-        const int64_t ooff = sdp->ooff;
+        if (newtile) {
+            const int a = ct.a;
+            const int aend = min(a + T, ct.n);
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int n = a + (r << WSH) + tid;
-            if (n < aend) {
-                if (p.out_mask & 2u) p.max_snr[ooff + n] = best[r];
-                if (p.out_mask & 4u) p.best_h[ooff + n] = (uint8_t)(1u << (st[r] & 255));
+            for (int r = 0; r < R; ++r) {
+                const int n = a + (r << WSH) + tid;
+                if (n < aend) {
+                    if (p.out_mask & 2u) p.max_snr[ct.xoff + n] = best[r];
+                    if (p.out_mask & 4u) p.best_h[ct.xoff + n] = (uint8_t)(1u << (st[r] & 255));
+                }
+                acc[r] = 0.0f;
+                best[r] = 0.0f;
+                st[r] = 0;
             }
         }
+        if (!more) break;
+        __syncthreads();   // every thread is done with this piece
+        stage.store(lds, np.nv);
         __syncthreads();
+        if (newtile) {
+            t = tn;
+            ct = ft;
+            pe = ct.pbeg + ct.pcount;
+            pi = ct.pbeg;
+            ++c;
+            tn = uniform(s_claim[c & 1]);
+            if (tid == 0) s_claim[(c + 1) & 1] = claim_tile(p, cq, visited);
+            if (tn >= 0) ft = p.tiles[tn];
+        } else {
+            ++pi;
+        }
+        cp = np;
     }
 }
 
@@ -375,56 +379,68 @@ __global__ __launch_bounds__(WG) void k_hrms1d_fund(const Run1DParams p)
 // adds its terms in the order i = 1..H; each level keeps its own sum.
 //
 // Neighbouring outputs read neighbouring (often equal) bins -- the stride is
-// k / Lh <= 1 -- so the loads of a wavefront are coalesced and are issued
-// straight from global memory, R outputs per thread in flight.
+// k / Lh <= 1 -- so the loads of a wavefront are coalesced; they are issued
+// straight from global memory as 32-bit-offset buffer loads, R outputs per
+// thread in flight.
 // --------------------------------------------------------------------------
+template <int DT>
+__device__ __forceinline__ float buffer_elem(__amdgpu_buffer_rsrc_t rs, int pos)
+{
+    if constexpr (DT == kF32) {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, pos * 4, 0, 0));
+    } else if constexpr (DT == kF16) {
+        return h2f(__builtin_amdgcn_raw_buffer_load_b16(rs, pos * 2, 0, 0));
+    } else {
+        return bf2f(__builtin_amdgcn_raw_buffer_load_b16(rs, pos * 2, 0, 0));
+    }
+}
+
+constexpr int kBufferFlags = 0x00020000;   // raw (untyped) 32-bit buffer, gfx9 word 3
+
 template <int DT, int WG, int R, int CB>
 __global__ __launch_bounds__(WG) void k_hrms1d_eq1(const Run1DParams p)
 {
     constexpr int T = WG * R;
-    __shared__ int s_item;
-
     const int tid = (int)threadIdx.x;
-    int queue = (int)(blockIdx.x % (unsigned)p.nqueues), visited = 0;
-    for (;;) {
-        if (tid == 0) s_item = take_tile(p, queue, visited);
-        __syncthreads();
-        const int item = uniform(s_item);
-        if (item < 0) break;
-        const Tile tl = p.tiles[item];
-        const int spec = uniform(tl.spec);
-        const int a = uniform(tl.start);
-        const SpecDesc* sdp = p.spec + spec;
-        const int64_t xoff = sdp->xoff;
-        const int N = uniform(sdp->n);
-        const int nl = uniform(sdp->nlev);
-        const LevelConst* lcon = p.consts + (int64_t)spec * kMaxLevels;
+    __shared__ int s_claim[2];
+    int cq = (int)(blockIdx.x % (unsigned)p.nqueues), visited = 0;
+    if (tid == 0) s_claim[0] = claim_tile(p, cq, visited);
+    __syncthreads();
+    int t = uniform(s_claim[0]);
+    for (int c = 0; t >= 0; ++c) {
+        // claim the following tile now; it is read after this tile's barrier
+        if (tid == 0) s_claim[(c + 1) & 1] = claim_tile(p, cq, visited);
+        const TileRec ct = p.tiles[t];
+        const int a = ct.a;
+        const int N = ct.n;
+        const int nl = ct.nlev;
         const int aend = min(a + T, N);
         const int sh = nl - 1;
         const int Lh = 1 << sh;
         const unsigned half = (unsigned)Lh >> 1;
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)(static_cast<const char*>(p.x) + ct.xoff * Elem<DT>::kBytes), (short)0,
+            N * Elem<DT>::kBytes, kBufferFlags);
 
         float acc[R][kMaxLevels];
+        unsigned nn[R], tk[R];
+        bool act[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
 #pragma unroll
             for (int l = 0; l < kMaxLevels; ++l) acc[r][l] = 0.0f;
-        }
-        unsigned nn[R];
-        bool act[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
             const int n = a + r * WG + tid;
             act[r] = n < aend;
             nn[r] = act[r] ? (unsigned)n : (unsigned)a;
+            tk[r] = half;   // n k + Lh/2 for k = 0
         }
         for (int k = 1; k <= Lh; ++k) {
             float v[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
+                tk[r] += nn[r];
                 // round(n k / Lh), halves up: floor((n k + Lh/2) / Lh)
-                const int pos = (int)((nn[r] * (unsigned)k + half) >> sh);
-                v[r] = load_scalar<DT>(p.x, xoff + pos);
+                v[r] = buffer_elem<DT>(rs, (int)(tk[r] >> sh));
             }
             const int lmin = sh - __builtin_ctz((unsigned)k);
 #pragma unroll
@@ -436,7 +452,6 @@ __global__ __launch_bounds__(WG) void k_hrms1d_eq1(const Run1DParams p)
             }
         }
 
-        const int64_t ooff = sdp->ooff;
         float best[R];
         int bl[R];
 #pragma unroll
@@ -447,8 +462,8 @@ __global__ __launch_bounds__(WG) void k_hrms1d_eq1(const Run1DParams p)
 #pragma unroll
         for (int l = 0; l < kMaxLevels; ++l) {
             if (l < nl) {
-                const LevelConst c = lcon[l];
-                const int64_t ho = sdp->hoff[l];
+                const LevelConst c = p.consts[(int64_t)ct.spec * kMaxLevels + l];
+                const int64_t ho = p.spec[ct.spec].hoff[l];
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const float hv = acc[r][l] * c.rh;
@@ -464,11 +479,12 @@ __global__ __launch_bounds__(WG) void k_hrms1d_eq1(const Run1DParams p)
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             if (act[r]) {
-                if (p.out_mask & 2u) p.max_snr[ooff + nn[r]] = best[r];
-                if (p.out_mask & 4u) p.best_h[ooff + nn[r]] = (uint8_t)(1u << bl[r]);
+                if (p.out_mask & 2u) p.max_snr[ct.xoff + nn[r]] = best[r];
+                if (p.out_mask & 4u) p.best_h[ct.xoff + nn[r]] = (uint8_t)(1u << bl[r]);
             }
         }
         __syncthreads();
+        t = uniform(s_claim[(c + 1) & 1]);
     }
 }
 

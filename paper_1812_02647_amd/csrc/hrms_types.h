@@ -1,0 +1,49 @@
+// hrms_types.h -- plain data records shared by the host planner and the
+// gfx950 kernels (no HIP dependency, so the planner can be checked with a
+// host compiler alone). Not part of the public ABI.
+#pragma once
+
+#include <cstdint>
+
+namespace hrms {
+
+constexpr int kMaxLevels = 6;
+
+// One spectrum of a 1D batch (or one row group of a plane), as the kernels see it.
+struct SpecDesc {
+    int64_t xoff;               // first input bin in x (elements)
+    int64_t ooff;               // first bin of max_snr / best_h
+    int64_t hoff[kMaxLevels];   // first float of each level plane in h, -1 if absent
+    int32_t n;                  // bins
+    int32_t nlev;               // levels: log2(Hmax) + 1
+};
+
+// A tile of consecutive outputs [a, a + T) of one spectrum (1D kernels).
+struct TileRec {
+    int64_t xoff;    // first bin of the spectrum in x (and in max_snr / best_h)
+    int32_t n;       // bins of the spectrum
+    int32_t a;       // first output of the tile
+    int32_t pbeg;    // first piece record of the tile (eq. (2)-(4))
+    int32_t pcount;  // piece records of the tile
+    int32_t spec;    // spectrum index (constants, h offsets)
+    int32_t nlev;    // levels of the spectrum
+};
+
+// One LDS piece of a tile (eq. (2)-(4)): harmonic i for the outputs
+// [a + n0r, a + n1r), staging the bins [p0, p0 + nv * 16 / sizeof(elem)).
+struct PieceRec {
+    int32_t p0;      // first staged bin, relative to the spectrum, 16-byte aligned in x
+    int32_t nr;      // n0r (bits 0..15) | n1r (bits 16..31)
+    int32_t ih;      // i (bits 0..7) | level(i) (bits 8..15) | snapshot flag (bit 16)
+    int32_t nv;      // 16-byte vectors to stage
+};
+
+// A segment of one spectrum for the statistics reduction.
+struct Seg {
+    int32_t spec;
+    int32_t start;
+    int32_t len;
+    int32_t pad;
+};
+
+}  // namespace hrms
