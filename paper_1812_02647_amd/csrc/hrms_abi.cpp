@@ -75,6 +75,13 @@ struct Plan1D {
     DeviceBuf d_spec, d_tiles, d_pieces, d_qbeg, d_segs, d_seg_first, d_partial, d_consts,
         d_counter;
     bool uploaded = false;
+    // instantiated launch sequence for the most recent argument pointers
+    hipGraphExec_t gexec = nullptr;
+    std::vector<const void*> gkey;
+    ~Plan1D()
+    {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+    }
 };
 
 // A 2D plane: its rows as statistics "spectra", combined into one (mu, sigma).
@@ -98,13 +105,29 @@ struct PlanQ {
     DeviceBuf d_spec, d_segs, d_seg_first, d_partial, d_inv;
 };
 
+// Tuned launch shape of a class of 1D batches.
+struct TuneKey {
+    int variant, dtype, hmax, lenlog;
+    bool operator<(const TuneKey& o) const
+    {
+        if (variant != o.variant) return variant < o.variant;
+        if (dtype != o.dtype) return dtype < o.dtype;
+        if (hmax != o.hmax) return hmax < o.hmax;
+        return lenlog < o.lenlog;
+    }
+};
+
 }  // namespace
 
 struct hrms_ctx {
     int device = 0;
     int cu_count = 0;
+    std::string arch;
     std::string err;
     std::string tune_path;
+    std::map<TuneKey, Shape1D> tune;
+    hipStream_t capture = nullptr;   // private stream for graph capture
+    bool graphs = true;
     std::vector<std::unique_ptr<Plan1D>> plans;   // most recent last
     std::unique_ptr<Plan2D> plan2d;
     std::unique_ptr<PlanQ> planq;
@@ -581,6 +604,162 @@ int get_plan_1d(hrms_ctx* c, const hrms_run1d_args* a, const Shape1D& shape, hip
     return HRMS_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// Launch shapes: tuned table, environment override for debugging, default
+// ---------------------------------------------------------------------------
+
+TuneKey tune_key(const hrms_run1d_args* a)
+{
+    int hm = 0;
+    const int64_t total = a->offsets[a->n_spectra];
+    for (int s = 0; s < a->n_spectra; ++s) hm = std::max(hm, (int)(a->hmax ? a->hmax[s] : a->hmax_all));
+    const int64_t mean = std::max<int64_t>(1, total / a->n_spectra);
+    int lg = 0;
+    while ((int64_t(1) << (lg + 1)) <= mean) ++lg;
+    return TuneKey{a->variant, a->dtype, hm, lg};
+}
+
+Shape1D shape_for(hrms_ctx* c, const hrms_run1d_args* a)
+{
+    if (const char* f = std::getenv("HRMS_FORCE_SHAPE")) {
+        Shape1D fs{};
+        if (std::sscanf(f, "%d:%d:%d", &fs.wg, &fs.r, &fs.chunk) == 3 &&
+            hrms1d_shape_supported(a->variant, fs))
+            return fs;
+    }
+    auto it = c->tune.find(tune_key(a));
+    if (it != c->tune.end() && hrms1d_shape_supported(a->variant, it->second)) return it->second;
+    return default_shape(a->variant);
+}
+
+const char* kTuneMagic = "hrms-tune-v1";
+
+// Tune cache: a header line "hrms-tune-v1 <arch> <CUs>" then one line per
+// batch class "variant dtype hmax lenlog wg r chunk". A file whose header does
+// not match this device, or a malformed line, is ignored.
+void load_tune(hrms_ctx* c)
+{
+    FILE* f = std::fopen(c->tune_path.c_str(), "r");
+    if (!f) return;
+    char magic[32] = {0}, arch[64] = {0};
+    int cus = 0;
+    if (std::fscanf(f, "%31s %63s %d", magic, arch, &cus) == 3 && std::strcmp(magic, kTuneMagic) == 0 &&
+        c->arch == arch && cus == c->cu_count) {
+        std::map<TuneKey, Shape1D> t;
+        TuneKey k{};
+        Shape1D sh{};
+        int got;
+        while ((got = std::fscanf(f, "%d %d %d %d %d %d %d", &k.variant, &k.dtype, &k.hmax, &k.lenlog,
+                                  &sh.wg, &sh.r, &sh.chunk)) == 7) {
+            if (hrms1d_shape_supported(k.variant, sh)) t[k] = sh;
+        }
+        if (got == EOF) c->tune.swap(t);
+    }
+    std::fclose(f);
+}
+
+void save_tune(hrms_ctx* c)
+{
+    const std::string tmp = c->tune_path + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;
+    std::fprintf(f, "%s %s %d\n", kTuneMagic, c->arch.c_str(), c->cu_count);
+    for (const auto& kv : c->tune)
+        std::fprintf(f, "%d %d %d %d %d %d %d\n", kv.first.variant, kv.first.dtype, kv.first.hmax,
+                     kv.first.lenlog, kv.second.wg, kv.second.r, kv.second.chunk);
+    const bool ok = std::fclose(f) == 0;
+    if (ok) std::rename(tmp.c_str(), c->tune_path.c_str());
+}
+
+// Enqueues statistics (or not), constants and the harmonic sum.
+hipError_t enqueue_1d(const hrms_run1d_args* a, Plan1D* P, const Shape1D& shape, hipStream_t stream)
+{
+    hipError_t e;
+    const bool compute = a->stats_mode == HRMS_STATS_COMPUTE;
+    if (compute) {
+        StatsParams sp{a->x, (const SpecDesc*)P->d_spec.p, (const Seg*)P->d_segs.p,
+                       (double*)P->d_partial.p, (int32_t)P->segs.size()};
+        if ((e = launch_stats_partial(a->dtype, sp, stream)) != hipSuccess) return e;
+    }
+    ConstsParams cp{};
+    cp.spec = (const SpecDesc*)P->d_spec.p;
+    cp.segs = (const Seg*)P->d_segs.p;
+    cp.seg_first = (const int32_t*)P->d_seg_first.p;
+    cp.partial = (const double*)P->d_partial.p;
+    cp.stats = a->stats;
+    cp.consts = (LevelConst*)P->d_consts.p;
+    cp.user_consts = a->snr_consts;
+    cp.counters = (unsigned int*)P->d_counter.p;
+    cp.n_spec = a->n_spectra;
+    cp.variant = a->variant;
+    cp.compute_stats = compute ? 1 : 0;
+    if ((e = launch_consts(cp, stream)) != hipSuccess) return e;
+    if (a->out_mask != 0) {
+        Run1DParams rp{};
+        rp.x = a->x;
+        rp.spec = (const SpecDesc*)P->d_spec.p;
+        rp.tiles = (const TileRec*)P->d_tiles.p;
+        rp.pieces = (const PieceRec*)P->d_pieces.p;
+        rp.consts = (const LevelConst*)P->d_consts.p;
+        rp.h = a->h;
+        rp.max_snr = a->max_snr;
+        rp.best_h = a->best_h;
+        rp.qbeg = (const int32_t*)P->d_qbeg.p;
+        rp.counters = (unsigned int*)P->d_counter.p;
+        rp.nqueues = P->nqueues;
+        rp.out_mask = a->out_mask;
+        if ((e = launch_hrms1d(a->variant, a->dtype, shape, rp, P->grid, stream)) != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
+// Runs one batch with the given shape; with graphs on, the launch sequence is
+// captured once per plan and argument pointers and replayed afterwards.
+int run_1d_with(hrms_ctx* h, const hrms_run1d_args* a, hipStream_t stream, const Shape1D& shape,
+                bool graphs)
+{
+    Plan1D* P = nullptr;
+    int st = get_plan_1d(h, a, shape, stream, &P);
+    if (st != HRMS_OK) return st;
+    hipError_t e;
+    if (!graphs) {
+        if ((e = enqueue_1d(a, P, shape, stream)) != hipSuccess) return hip_fail(h, e, "launch");
+        return HRMS_OK;
+    }
+    const std::vector<const void*> key = {a->x, a->stats, a->snr_consts, a->h, a->max_snr,
+                                          a->best_h, (const void*)(intptr_t)a->stats_mode,
+                                          (const void*)(intptr_t)a->out_mask};
+    if (!P->gexec || P->gkey != key) {
+        if (!h->capture &&
+            (e = hipStreamCreateWithFlags(&h->capture, hipStreamNonBlocking)) != hipSuccess)
+            return hip_fail(h, e, "hipStreamCreate");
+        if (P->gexec) {
+            (void)hipGraphExecDestroy(P->gexec);
+            P->gexec = nullptr;
+        }
+        if ((e = hipStreamBeginCapture(h->capture, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+            return hip_fail(h, e, "hipStreamBeginCapture");
+        const hipError_t le = enqueue_1d(a, P, shape, h->capture);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(h->capture, &g);
+        if (le != hipSuccess || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return hip_fail(h, le != hipSuccess ? le : e, "graph capture");
+        }
+        e = hipGraphInstantiate(&P->gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            P->gexec = nullptr;
+            return hip_fail(h, e, "hipGraphInstantiate");
+        }
+        P->gkey = key;
+    }
+    if ((e = hipGraphLaunch(P->gexec, stream)) != hipSuccess) return hip_fail(h, e, "hipGraphLaunch");
+    return HRMS_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -627,7 +806,12 @@ int hrms_create(hrms_handle* out, int device_ordinal, const char* tune_cache_pat
     if (!c) return fail(nullptr, HRMS_E_NOMEM, "host allocation failed");
     c->device = device_ordinal;
     c->cu_count = prop.multiProcessorCount;
-    if (tune_cache_path) c->tune_path = tune_cache_path;
+    c->arch = std::string(prop.gcnArchName).substr(0, std::string(prop.gcnArchName).find(':'));
+    if (const char* g = std::getenv("HRMS_NO_GRAPH")) c->graphs = !(g[0] && g[0] != '0');
+    if (tune_cache_path) {
+        c->tune_path = tune_cache_path;
+        load_tune(c);
+    }
     *out = c;
     return HRMS_OK;
 }
@@ -642,6 +826,7 @@ int hrms_destroy(hrms_handle h)
     h->plans.clear();
     h->plan2d.reset();
     h->planq.reset();
+    if (h->capture) (void)hipStreamDestroy(h->capture);
     (void)hipSetDevice(cur);
     delete h;
     return HRMS_OK;
@@ -673,57 +858,60 @@ int hrms_run_1d(hrms_handle h, const hrms_run1d_args* a, void* hip_stream)
     if (st != HRMS_OK) return st;
     hipError_t e = hipSetDevice(h->device);
     if (e != hipSuccess) return hip_fail(h, e, "hipSetDevice");
-    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
-    Shape1D shape = default_shape(a->variant);
-    if (const char* f = std::getenv("HRMS_FORCE_SHAPE")) {
-        // debugging override "wg:r:chunk", ignored unless compiled in
-        Shape1D fs{};
-        if (std::sscanf(f, "%d:%d:%d", &fs.wg, &fs.r, &fs.chunk) == 3 &&
-            hrms1d_shape_supported(a->variant, fs))
-            shape = fs;
-    }
-    Plan1D* P = nullptr;
-    st = get_plan_1d(h, a, shape, stream, &P);
+    return run_1d_with(h, a, static_cast<hipStream_t>(hip_stream), shape_for(h, a), h->graphs);
+}
+
+int hrms_autotune_1d(hrms_handle h, const hrms_run1d_args* a, void* hip_stream, int reps,
+                     int32_t* chosen)
+{
+    if (!h) return fail(nullptr, HRMS_E_INVAL, "handle is NULL");
+    h->err.clear();
+    int st = validate_1d(h, a, true);
     if (st != HRMS_OK) return st;
-
-    const bool compute = a->stats_mode == HRMS_STATS_COMPUTE;
-    if (compute) {
-        StatsParams sp{a->x, (const SpecDesc*)P->d_spec.p, (const Seg*)P->d_segs.p,
-                       (double*)P->d_partial.p, (int32_t)P->segs.size()};
-        if ((e = launch_stats_partial(a->dtype, sp, stream)) != hipSuccess)
-            return hip_fail(h, e, "statistics launch");
+    if (reps < 1 || reps > 1000) return fail(h, HRMS_E_INVAL, "reps must be in 1..1000");
+    hipError_t e = hipSetDevice(h->device);
+    if (e != hipSuccess) return hip_fail(h, e, "hipSetDevice");
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    Shape1D shapes[16];
+    const int ns = std::min(16, hrms1d_shapes(a->variant, shapes, 16));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return hip_fail(h, e, "hipEventCreate");
     }
-    ConstsParams cp{};
-    cp.spec = (const SpecDesc*)P->d_spec.p;
-    cp.segs = (const Seg*)P->d_segs.p;
-    cp.seg_first = (const int32_t*)P->d_seg_first.p;
-    cp.partial = (const double*)P->d_partial.p;
-    cp.stats = a->stats;
-    cp.consts = (LevelConst*)P->d_consts.p;
-    cp.user_consts = a->snr_consts;
-    cp.counters = (unsigned int*)P->d_counter.p;
-    cp.n_spec = a->n_spectra;
-    cp.variant = a->variant;
-    cp.compute_stats = compute ? 1 : 0;
-    if ((e = launch_consts(cp, stream)) != hipSuccess) return hip_fail(h, e, "constants launch");
-
-    if (a->out_mask != 0) {
-        Run1DParams rp{};
-        rp.x = a->x;
-        rp.spec = (const SpecDesc*)P->d_spec.p;
-        rp.tiles = (const TileRec*)P->d_tiles.p;
-        rp.pieces = (const PieceRec*)P->d_pieces.p;
-        rp.consts = (const LevelConst*)P->d_consts.p;
-        rp.h = a->h;
-        rp.max_snr = a->max_snr;
-        rp.best_h = a->best_h;
-        rp.qbeg = (const int32_t*)P->d_qbeg.p;
-        rp.counters = (unsigned int*)P->d_counter.p;
-        rp.nqueues = P->nqueues;
-        rp.out_mask = a->out_mask;
-        if ((e = launch_hrms1d(a->variant, a->dtype, shape, rp, P->grid, stream)) != hipSuccess)
-            return hip_fail(h, e, "harmonic-sum launch");
+    float best_ms = 0.0f;
+    int best = -1;
+    for (int k = 0; k < ns && st == HRMS_OK; ++k) {
+        st = run_1d_with(h, a, stream, shapes[k], false);   // plan build + warm-up
+        if (st != HRMS_OK) break;
+        if ((e = hipEventRecord(e0, stream)) != hipSuccess) {
+            st = hip_fail(h, e, "hipEventRecord");
+            break;
+        }
+        for (int r = 0; r < reps && st == HRMS_OK; ++r) st = run_1d_with(h, a, stream, shapes[k], false);
+        if (st != HRMS_OK) break;
+        float ms = 0.0f;
+        if ((e = hipEventRecord(e1, stream)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess ||
+            (e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) {
+            st = hip_fail(h, e, "timing");
+            break;
+        }
+        if (best < 0 || ms < best_ms) {
+            best_ms = ms;
+            best = k;
+        }
     }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != HRMS_OK) return st;
+    if (best < 0) return fail(h, HRMS_E_UNSUPPORTED, "no launch shape compiled for this variant");
+    h->tune[tune_key(a)] = shapes[best];
+    if (chosen) {
+        chosen[0] = shapes[best].wg;
+        chosen[1] = shapes[best].r;
+        chosen[2] = shapes[best].chunk;
+    }
+    if (!h->tune_path.empty()) save_tune(h);
     return HRMS_OK;
 }
 

@@ -34,7 +34,6 @@ namespace {
 
 constexpr int kEq1 = 0, kMax = 1, kFreqbin = 2, kGreedy = 3;
 constexpr int kF32 = 0, kF16 = 1, kBF16 = 2;
-constexpr int kHalo = 32;
 
 template <int DT>
 struct Elem {
@@ -103,6 +102,23 @@ __device__ __forceinline__ int pidx(int k) { return k + (k >> 5); }
 __device__ __forceinline__ int level_of(int i) { return 32 - __clz(i - 1); }
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Read-only record through the constant address space: with a uniform index
+// this is a scalar (SMEM) load through the scalar cache, which the compiler
+// cannot otherwise prove safe while the kernel also stores to global memory.
+template <typename T>
+__device__ __forceinline__ T ldc(const T* ptr)
+{
+    static_assert(sizeof(T) % 4 == 0, "records are whole words");
+    typedef const __attribute__((address_space(4))) uint32_t* cword;
+    const cword w = (cword)(ptr);
+    uint32_t buf[sizeof(T) / 4];
+#pragma unroll
+    for (unsigned k = 0; k < sizeof(T) / 4; ++k) buf[k] = w[k];
+    T out;
+    __builtin_memcpy(&out, buf, sizeof(T));
+    return out;
+}
 
 // Chunk start for absolute alignment of the 16-byte loads.
 template <int DT>
@@ -242,11 +258,11 @@ __global__ __launch_bounds__(WG) void k_hrms1d_fund(const Run1DParams p)
     int tn = uniform(s_claim[1]);
     int c = 1;   // index of the tile that tn names
 
-    TileRec ct = p.tiles[t];
+    TileRec ct = ldc(p.tiles + t);
     int pi = ct.pbeg, pe = ct.pbeg + ct.pcount;
-    PieceRec cp = p.pieces[pi];
+    PieceRec cp = ldc(p.pieces + pi);
     TileRec ft = ct;   // record of tile tn, fetched a whole tile ahead of its use
-    if (tn >= 0) ft = p.tiles[tn];
+    if (tn >= 0) ft = ldc(p.tiles + tn);
 
     float acc[R], best[R];
     int st[R];   // best level (bits 0..7) | Greedy offset j (bits 8..)
@@ -268,7 +284,7 @@ __global__ __launch_bounds__(WG) void k_hrms1d_fund(const Run1DParams p)
         const TileRec& nt = newtile ? ft : ct;
         PieceRec np = cp;
         if (more) {
-            np = p.pieces[newtile ? nt.pbeg : pi + 1];
+            np = ldc(p.pieces + (newtile ? nt.pbeg : pi + 1));
             stage.load(p.x, nt.xoff, nt.n, np.p0, np.nv);
         }
 
@@ -283,11 +299,11 @@ __global__ __launch_bounds__(WG) void k_hrms1d_fund(const Run1DParams p)
             float m = 0.0f, qq = 0.0f, rh = 0.0f;
             int64_t ho = 0;
             if (snap) {
-                const LevelConst c = p.consts[(int64_t)ct.spec * kMaxLevels + li];
+                const LevelConst c = ldc(p.consts + (int64_t)ct.spec * kMaxLevels + li);
                 m = c.m;
                 qq = c.q;
                 rh = c.rh;
-                ho = p.spec[ct.spec].hoff[li];
+                ho = ldc(p.spec[ct.spec].hoff + li);
             }
             const int r0 = (n0 - a) >> WSH, r1 = (n1 - 1 - a) >> WSH;
 #pragma unroll
@@ -362,7 +378,7 @@ __global__ __launch_bounds__(WG) void k_hrms1d_fund(const Run1DParams p)
             ++c;
             tn = uniform(s_claim[c & 1]);
             if (tid == 0) s_claim[(c + 1) & 1] = claim_tile(p, cq, visited);
-            if (tn >= 0) ft = p.tiles[tn];
+            if (tn >= 0) ft = ldc(p.tiles + tn);
         } else {
             ++pi;
         }
@@ -410,7 +426,7 @@ __global__ __launch_bounds__(WG) void k_hrms1d_eq1(const Run1DParams p)
     for (int c = 0; t >= 0; ++c) {
         // claim the following tile now; it is read after this tile's barrier
         if (tid == 0) s_claim[(c + 1) & 1] = claim_tile(p, cq, visited);
-        const TileRec ct = p.tiles[t];
+        const TileRec ct = ldc(p.tiles + t);
         const int a = ct.a;
         const int N = ct.n;
         const int nl = ct.nlev;
@@ -462,8 +478,8 @@ __global__ __launch_bounds__(WG) void k_hrms1d_eq1(const Run1DParams p)
 #pragma unroll
         for (int l = 0; l < kMaxLevels; ++l) {
             if (l < nl) {
-                const LevelConst c = p.consts[(int64_t)ct.spec * kMaxLevels + l];
-                const int64_t ho = p.spec[ct.spec].hoff[l];
+                const LevelConst c = ldc(p.consts + (int64_t)ct.spec * kMaxLevels + l);
+                const int64_t ho = ldc(p.spec[ct.spec].hoff + l);
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const float hv = acc[r][l] * c.rh;

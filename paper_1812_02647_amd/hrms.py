@@ -32,7 +32,8 @@ VARIANTS = {"eq1": HRMS_EQ1, "max": HRMS_MAX, "freqbin": HRMS_FREQBIN, "greedy":
 DTYPES = {"f32": HRMS_F32, "f16": HRMS_F16, "bf16": HRMS_BF16}
 
 EXPORTED = ["hrms_create", "hrms_destroy", "hrms_layout_1d", "hrms_layout_2d", "hrms_run_1d",
-            "hrms_run_2d", "hrms_quantize", "hrms_strerror", "hrms_last_error"]
+            "hrms_autotune_1d", "hrms_run_2d", "hrms_quantize", "hrms_strerror",
+            "hrms_last_error"]
 
 
 class hrms_run1d_args(C.Structure):
@@ -117,6 +118,9 @@ def lib():
         L.hrms_layout_2d.restype = i32
         L.hrms_run_1d.argtypes = [vp, C.POINTER(hrms_run1d_args), vp]
         L.hrms_run_1d.restype = i32
+        L.hrms_autotune_1d.argtypes = [vp, C.POINTER(hrms_run1d_args), vp, i32,
+                                       C.POINTER(C.c_int32)]
+        L.hrms_autotune_1d.restype = i32
         L.hrms_run_2d.argtypes = [vp, C.POINTER(hrms_run2d_args), vp]
         L.hrms_run_2d.restype = i32
         L.hrms_quantize.argtypes = [vp, C.POINTER(hrms_quantize_args), vp]
@@ -174,6 +178,15 @@ def hrms_layout_2d(args: hrms_run2d_args):
 
 def hrms_run_1d(handle, args: hrms_run1d_args, stream=None) -> None:
     _check(lib().hrms_run_1d(handle, C.byref(args), _stream_ptr(stream)), handle)
+
+
+def hrms_autotune_1d(handle, args: hrms_run1d_args, stream=None, reps: int = 3):
+    """Times every compiled launch shape on this batch and keeps the fastest;
+    returns (wg, r, chunk)."""
+    chosen = (C.c_int32 * 3)()
+    _check(lib().hrms_autotune_1d(handle, C.byref(args), _stream_ptr(stream), reps, chosen),
+           handle)
+    return tuple(chosen)
 
 
 def hrms_run_2d(handle, args: hrms_run2d_args, stream=None) -> None:
