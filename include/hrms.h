@@ -172,21 +172,23 @@ int hrms_layout_2d(const hrms_run2d_args* a, int64_t* plane_offsets, int64_t* h_
 
 /* Harmonic sum of a 1D batch: statistics (unless provided), SNR constants,
  * then every level of every spectrum in one persistent launch. `hip_stream` is
- * a hipStream_t or NULL. The three launches are captured into a HIP graph the
- * first time a plan (batch signature) meets a set of argument pointers and the
- * graph is replayed afterwards (environment HRMS_NO_GRAPH=1 enqueues them
- * directly instead). */
+ * a hipStream_t or NULL. The launches (statistics, constants, one or two
+ * harmonic-sum kernels) are captured into a HIP graph the first time a plan
+ * (batch signature) meets a set of argument pointers and the graph is replayed
+ * afterwards (environment HRMS_NO_GRAPH=1 enqueues them directly instead). */
 int hrms_run_1d(hrms_handle h, const hrms_run1d_args* a, void* hip_stream);
 
 /* Picks the fastest compiled launch shape (threads per workgroup, outputs per
- * thread, LDS chunk) for batches like `a` -- same variant, storage type, largest
+ * thread, LDS chunk or 0 for the gathered form, and the lowest top level of the
+ * bands handed to a second launch of the LDS form, 0 for none) for batches
+ * like `a` -- same variant, storage type, largest
  * Hmax and mean spectrum length within a factor of two -- by timing `reps` runs
  * of each shape on `hip_stream` (the call blocks until they finish). Later
  * hrms_run_1d calls on the handle use it, and it is written to the handle's
  * tune cache file if one was given. The shape does not change any result bit:
  * every output adds its harmonics in the same order whatever the shape. The
- * outputs of `a` hold the result of the last run. chosen (host, may be NULL)
- * receives {wg, r, chunk}. */
+ * outputs of `a` hold the result of the last run. chosen (host, may be NULL,
+ * else four entries) receives {wg, r, chunk, top}. */
 int hrms_autotune_1d(hrms_handle h, const hrms_run1d_args* a, void* hip_stream, int reps,
                      int32_t* chosen);
 

@@ -64,16 +64,15 @@ struct Plan1D {
     Shape1D shape{};
     // host mirrors (kept alive for the asynchronous uploads)
     std::vector<SpecDesc> spec;
-    std::vector<TileRec> tiles;
-    std::vector<PieceRec> pieces;
-    std::vector<int32_t> qbeg;
+    std::vector<TileRec> tiles, tiles_top;   // main launch, top-band launch
+    std::vector<int32_t> qbeg, qbeg_top;
     std::vector<Seg> segs;
     std::vector<int32_t> seg_first;
-    int grid = 0;
+    int grid = 0, grid_top = 0;
     int nqueues = 1;
     // device
-    DeviceBuf d_spec, d_tiles, d_pieces, d_qbeg, d_segs, d_seg_first, d_partial, d_consts,
-        d_counter;
+    DeviceBuf d_spec, d_tiles, d_qbeg, d_tiles_top, d_qbeg_top, d_segs, d_seg_first, d_partial,
+        d_consts, d_counter;
     bool uploaded = false;
     // instantiated launch sequence for the most recent argument pointers
     hipGraphExec_t gexec = nullptr;
@@ -286,8 +285,11 @@ int64_t layout_2d_into(const hrms_run2d_args* a, int64_t* plane_offsets)
 
 Shape1D default_shape(int variant)
 {
-    if (variant == HRMS_EQ1) return Shape1D{256, 8, 0};
-    return Shape1D{256, 8, 8192};
+    // measured on the 1000 x 2^21, Hmax = 32 batch
+    if (variant == HRMS_EQ1) return Shape1D{512, 8, 0, 0};
+    if (variant == HRMS_MAX) return Shape1D{1024, 8, 16384, 0};
+    if (variant == HRMS_GREEDY) return Shape1D{512, 8, 0, 0};
+    return Shape1D{512, 8, 0, 32};
 }
 
 template <typename T>
@@ -325,9 +327,15 @@ int build_plan_1d(hrms_ctx* c, const hrms_run1d_args* a, const Shape1D& shape, P
     // Tiles. Spectra are spread over one queue per XCD, balancing their total
     // cost; a queue lists its spectra one after the other (so the bins of a
     // spectrum stay in that XCD's L2 while its tiles run), each spectrum's
-    // tiles most expensive first. Piece lists depend only on (length, levels,
-    // alignment) and are shared by the spectra that agree on them.
-    const int T = shape.wg * shape.r;
+    // tiles most expensive first. For eq. (2)-(4) tiles are cut inside bands
+    // and a tile's cost is the positions it stages plus the terms it adds;
+    // with shape.top set, the bands whose top level is at least shape.top go
+    // to a second launch of the LDS form (kTopShape). Tile lists depend only
+    // on (length, levels, alignment) and are shared by the spectra that agree
+    // on them.
+    const bool eq1 = a->variant == HRMS_EQ1;
+    const int T = hrms1d_tile_outputs(a->variant, shape);
+    const int Ttop = hrms1d_tile_outputs(a->variant, kTopShape);
     const int vec = 16 / dtype_bytes(a->dtype);
     const int nq = (c->cu_count >= kMaxQueues && c->cu_count % kMaxQueues == 0) ? kMaxQueues : 1;
     struct Geo {
@@ -338,74 +346,101 @@ int build_plan_1d(hrms_ctx* c, const hrms_run1d_args* a, const Shape1D& shape, P
         }
     };
     struct TileSched {
-        int32_t pbeg, pcount;
+        int32_t a, aend, nlev;
+        bool top;
         int64_t cost;
     };
     std::map<Geo, std::vector<TileSched>> sched;
-    P->pieces.clear();
-    std::vector<std::vector<std::pair<int64_t, TileRec>>> per_spec(ns);
-    std::vector<std::pair<int64_t, int>> spec_cost(ns);
+    // [part][spectrum]: tiles (cost, record); part 0 = main launch, 1 = top bands
+    std::vector<std::vector<std::pair<int64_t, TileRec>>> per_spec[2];
+    per_spec[0].resize(ns);
+    per_spec[1].resize(ns);
+    std::vector<std::pair<int64_t, int>> spec_cost[2];
+    spec_cost[0].resize(ns);
+    spec_cost[1].resize(ns);
     for (int s = 0; s < ns; ++s) {
         const int n = P->spec[s].n;
         const Geo g{n, (int)P->nlev[s], (int)(a->offsets[s] % vec)};
         auto it = sched.find(g);
         if (it == sched.end()) {
             std::vector<TileSched> ts;
-            for (int t0 = 0; t0 < n; t0 += T) {
-                TileSched x{(int32_t)P->pieces.size(), 0, 0};
-                if (a->variant == HRMS_EQ1) {
-                    x.cost = (int64_t)std::min(T, n - t0) * ((1 << (g.nlev - 1)) + 1);
-                } else {
-                    x.cost = tile_pieces(a->variant, vec, shape.chunk, n, g.nlev, g.xmod, t0, T,
-                                         &P->pieces);
-                    x.pcount = (int32_t)P->pieces.size() - x.pbeg;
+            if (eq1) {
+                for (int t0 = 0; t0 < n; t0 += T) {
+                    const int te = std::min(t0 + T, n);
+                    ts.push_back(TileSched{t0, te, g.nlev, false,
+                                           (int64_t)(te - t0) * ((1 << (g.nlev - 1)) + 1)});
                 }
-                ts.push_back(x);
+            } else {
+                const int win = a->variant == HRMS_FREQBIN ? 0 : 1;
+                for (int l = 0; l < g.nlev; ++l) {
+                    const int hi = n >> l;
+                    const int lo = l + 1 < g.nlev ? (n >> (l + 1)) : 0;
+                    const int ht = 1 << l;
+                    const bool top = shape.top > 0 && ht >= shape.top;
+                    const Shape1D& sh = top ? kTopShape : shape;
+                    const int tt = top ? Ttop : T;
+                    const int64_t terms = a->variant == HRMS_MAX ? (int64_t)ht * (ht + 1) / 2 : ht;
+                    for (int t0 = lo; t0 < hi; t0 += tt) {
+                        const int te = std::min(t0 + tt, hi);
+                        int64_t staged = 0;
+                        if (sh.chunk > 0) {   // LDS form: positions staged
+                            SpanWalk w;
+                            w.begin(t0, te, ht, win, vec, sh.chunk, g.xmod);
+                            int cp, ce, cep;
+                            while (w.next(cp, ce, cep)) staged += ce - cp;
+                        }
+                        ts.push_back(TileSched{t0, te, l + 1, top, staged + (te - t0) * terms});
+                    }
+                }
             }
             it = sched.emplace(g, std::move(ts)).first;
         }
-        int64_t tot = 0;
-        for (size_t k = 0; k < it->second.size(); ++k) {
-            const TileSched& x = it->second[k];
+        int64_t tot[2] = {0, 0};
+        for (const TileSched& x : it->second) {
             TileRec tr;
             tr.xoff = a->offsets[s];
             tr.n = n;
-            tr.a = (int32_t)(k * (size_t)T);
-            tr.pbeg = x.pbeg;
-            tr.pcount = x.pcount;
+            tr.a = x.a;
+            tr.aend = x.aend;
             tr.spec = s;
-            tr.nlev = g.nlev;
-            per_spec[s].push_back({x.cost, tr});
-            tot += x.cost;
+            tr.nlev = x.nlev;
+            tr.pad = 0;
+            per_spec[x.top][s].push_back({x.cost, tr});
+            tot[x.top] += x.cost;
         }
-        std::stable_sort(per_spec[s].begin(), per_spec[s].end(),
-                         [](const std::pair<int64_t, TileRec>& x,
-                            const std::pair<int64_t, TileRec>& y) { return x.first > y.first; });
-        spec_cost[s] = {tot, s};
+        for (int part = 0; part < 2; ++part) {
+            std::stable_sort(per_spec[part][s].begin(), per_spec[part][s].end(),
+                             [](const std::pair<int64_t, TileRec>& x,
+                                const std::pair<int64_t, TileRec>& y) { return x.first > y.first; });
+            spec_cost[part][s] = {tot[part], s};
+        }
     }
-    std::stable_sort(spec_cost.begin(), spec_cost.end(),
-                     [](const std::pair<int64_t, int>& x, const std::pair<int64_t, int>& y) {
-                         return x.first > y.first;
-                     });
-    std::vector<std::vector<int>> qspec(nq);
-    std::vector<int64_t> qload(nq, 0);
-    for (const auto& sc : spec_cost) {
-        int best = 0;
-        for (int q = 1; q < nq; ++q)
-            if (qload[q] < qload[best]) best = q;
-        qspec[best].push_back(sc.second);
-        qload[best] += sc.first;
+    for (int part = 0; part < 2; ++part) {
+        std::stable_sort(spec_cost[part].begin(), spec_cost[part].end(),
+                         [](const std::pair<int64_t, int>& x, const std::pair<int64_t, int>& y) {
+                             return x.first > y.first;
+                         });
+        std::vector<std::vector<int>> qspec(nq);
+        std::vector<int64_t> qload(nq, 0);
+        for (const auto& sc : spec_cost[part]) {
+            int best = 0;
+            for (int q = 1; q < nq; ++q)
+                if (qload[q] < qload[best]) best = q;
+            qspec[best].push_back(sc.second);
+            qload[best] += sc.first;
+        }
+        std::vector<TileRec>& tiles = part ? P->tiles_top : P->tiles;
+        std::vector<int32_t>& qbeg = part ? P->qbeg_top : P->qbeg;
+        tiles.clear();
+        qbeg.assign(nq + 1, 0);
+        for (int q = 0; q < nq; ++q) {
+            qbeg[q] = (int32_t)tiles.size();
+            for (int sp : qspec[q])
+                for (const auto& ct : per_spec[part][sp]) tiles.push_back(ct.second);
+        }
+        qbeg[nq] = (int32_t)tiles.size();
     }
-    P->tiles.clear();
-    P->qbeg.assign(nq + 1, 0);
-    for (int q = 0; q < nq; ++q) {
-        P->qbeg[q] = (int32_t)P->tiles.size();
-        for (int s : qspec[q])
-            for (const auto& ct : per_spec[s]) P->tiles.push_back(ct.second);
-    }
-    P->qbeg[nq] = (int32_t)P->tiles.size();
     P->nqueues = nq;
-    if (P->pieces.empty()) P->pieces.push_back(PieceRec{0, 0, 0, 0});
 
     // statistics segments
     P->segs.clear();
@@ -418,20 +453,34 @@ int build_plan_1d(hrms_ctx* c, const hrms_run1d_args* a, const Shape1D& shape, P
     }
     P->seg_first[ns] = (int32_t)P->segs.size();
 
-    const int per_cu = hrms1d_max_blocks_per_cu(a->variant, a->dtype, shape);
-    if (per_cu <= 0) return fail(c, HRMS_E_HIP, "occupancy query failed for the 1D kernel");
-    // one resident wave of workgroups, the same number per queue
-    int64_t grid = std::min<int64_t>((int64_t)c->cu_count * per_cu, (int64_t)P->tiles.size());
-    if (grid >= nq) grid -= grid % nq;
-    P->grid = (int)std::max<int64_t>(grid, 1);
+    // one resident wave of workgroups per launch, the same number per queue
+    for (int part = 0; part < 2; ++part) {
+        const std::vector<TileRec>& tiles = part ? P->tiles_top : P->tiles;
+        int& grid_out = part ? P->grid_top : P->grid;
+        grid_out = 0;
+        if (tiles.empty()) continue;
+        hipError_t oe = hipSuccess;
+        const int per_cu =
+            hrms1d_max_blocks_per_cu(a->variant, a->dtype, part ? kTopShape : shape, &oe);
+        if (per_cu <= 0)
+            return hip_fail(c, oe != hipSuccess ? oe : hipErrorInvalidConfiguration,
+                            "occupancy query of the 1D kernel");
+        int64_t grid = std::min<int64_t>((int64_t)c->cu_count * per_cu, (int64_t)tiles.size());
+        if (grid >= nq) grid -= grid % nq;
+        grid_out = (int)std::max<int64_t>(grid, 1);
+    }
 
     hipError_t e;
     if ((e = upload(P->d_spec, P->spec, stream)) != hipSuccess) return hip_fail(c, e, "upload spec");
     if ((e = upload(P->d_tiles, P->tiles, stream)) != hipSuccess)
         return hip_fail(c, e, "upload tiles");
     if ((e = upload(P->d_qbeg, P->qbeg, stream)) != hipSuccess) return hip_fail(c, e, "upload qbeg");
-    if ((e = upload(P->d_pieces, P->pieces, stream)) != hipSuccess)
-        return hip_fail(c, e, "upload pieces");
+    if (!P->tiles_top.empty()) {
+        if ((e = upload(P->d_tiles_top, P->tiles_top, stream)) != hipSuccess)
+            return hip_fail(c, e, "upload tiles");
+        if ((e = upload(P->d_qbeg_top, P->qbeg_top, stream)) != hipSuccess)
+            return hip_fail(c, e, "upload qbeg");
+    }
     if ((e = upload(P->d_segs, P->segs, stream)) != hipSuccess) return hip_fail(c, e, "upload segs");
     if ((e = upload(P->d_seg_first, P->seg_first, stream)) != hipSuccess)
         return hip_fail(c, e, "upload seg_first");
@@ -439,7 +488,7 @@ int build_plan_1d(hrms_ctx* c, const hrms_run1d_args* a, const Shape1D& shape, P
         return hip_fail(c, e, "alloc partials");
     if ((e = P->d_consts.ensure((size_t)ns * kMaxLevels * sizeof(LevelConst))) != hipSuccess)
         return hip_fail(c, e, "alloc consts");
-    if ((e = P->d_counter.ensure(sizeof(unsigned int) * kMaxQueues)) != hipSuccess)
+    if ((e = P->d_counter.ensure(sizeof(unsigned int) * kCounterSlots)) != hipSuccess)
         return hip_fail(c, e, "alloc counters");
     P->uploaded = true;
     return HRMS_OK;
@@ -568,7 +617,8 @@ int validate_q(hrms_ctx* c, const hrms_quantize_args* a)
 bool same_signature(const Plan1D& P, const hrms_run1d_args* a, const Shape1D& shape)
 {
     if (P.variant != a->variant || P.dtype != a->dtype) return false;
-    if (P.shape.wg != shape.wg || P.shape.r != shape.r || P.shape.chunk != shape.chunk)
+    if (P.shape.wg != shape.wg || P.shape.r != shape.r || P.shape.chunk != shape.chunk ||
+        P.shape.top != shape.top)
         return false;
     if ((int)P.nlev.size() != a->n_spectra) return false;
     if (std::memcmp(P.offsets.data(), a->offsets, (a->n_spectra + 1) * sizeof(int64_t)) != 0)
@@ -624,7 +674,7 @@ Shape1D shape_for(hrms_ctx* c, const hrms_run1d_args* a)
 {
     if (const char* f = std::getenv("HRMS_FORCE_SHAPE")) {
         Shape1D fs{};
-        if (std::sscanf(f, "%d:%d:%d", &fs.wg, &fs.r, &fs.chunk) == 3 &&
+        if (std::sscanf(f, "%d:%d:%d:%d", &fs.wg, &fs.r, &fs.chunk, &fs.top) >= 3 &&
             hrms1d_shape_supported(a->variant, fs))
             return fs;
     }
@@ -633,11 +683,11 @@ Shape1D shape_for(hrms_ctx* c, const hrms_run1d_args* a)
     return default_shape(a->variant);
 }
 
-const char* kTuneMagic = "hrms-tune-v1";
+const char* kTuneMagic = "hrms-tune-v2";
 
-// Tune cache: a header line "hrms-tune-v1 <arch> <CUs>" then one line per
-// batch class "variant dtype hmax lenlog wg r chunk". A file whose header does
-// not match this device, or a malformed line, is ignored.
+// Tune cache: a header line "hrms-tune-v2 <arch> <CUs>" then one line per
+// batch class "variant dtype hmax lenlog wg r chunk top". A file whose header
+// does not match this device, or a malformed line, is ignored.
 void load_tune(hrms_ctx* c)
 {
     FILE* f = std::fopen(c->tune_path.c_str(), "r");
@@ -650,8 +700,8 @@ void load_tune(hrms_ctx* c)
         TuneKey k{};
         Shape1D sh{};
         int got;
-        while ((got = std::fscanf(f, "%d %d %d %d %d %d %d", &k.variant, &k.dtype, &k.hmax, &k.lenlog,
-                                  &sh.wg, &sh.r, &sh.chunk)) == 7) {
+        while ((got = std::fscanf(f, "%d %d %d %d %d %d %d %d", &k.variant, &k.dtype, &k.hmax,
+                                  &k.lenlog, &sh.wg, &sh.r, &sh.chunk, &sh.top)) == 8) {
             if (hrms1d_shape_supported(k.variant, sh)) t[k] = sh;
         }
         if (got == EOF) c->tune.swap(t);
@@ -666,8 +716,8 @@ void save_tune(hrms_ctx* c)
     if (!f) return;
     std::fprintf(f, "%s %s %d\n", kTuneMagic, c->arch.c_str(), c->cu_count);
     for (const auto& kv : c->tune)
-        std::fprintf(f, "%d %d %d %d %d %d %d\n", kv.first.variant, kv.first.dtype, kv.first.hmax,
-                     kv.first.lenlog, kv.second.wg, kv.second.r, kv.second.chunk);
+        std::fprintf(f, "%d %d %d %d %d %d %d %d\n", kv.first.variant, kv.first.dtype, kv.first.hmax,
+                     kv.first.lenlog, kv.second.wg, kv.second.r, kv.second.chunk, kv.second.top);
     const bool ok = std::fclose(f) == 0;
     if (ok) std::rename(tmp.c_str(), c->tune_path.c_str());
 }
@@ -700,7 +750,6 @@ hipError_t enqueue_1d(const hrms_run1d_args* a, Plan1D* P, const Shape1D& shape,
         rp.x = a->x;
         rp.spec = (const SpecDesc*)P->d_spec.p;
         rp.tiles = (const TileRec*)P->d_tiles.p;
-        rp.pieces = (const PieceRec*)P->d_pieces.p;
         rp.consts = (const LevelConst*)P->d_consts.p;
         rp.h = a->h;
         rp.max_snr = a->max_snr;
@@ -709,8 +758,17 @@ hipError_t enqueue_1d(const hrms_run1d_args* a, Plan1D* P, const Shape1D& shape,
         rp.counters = (unsigned int*)P->d_counter.p;
         rp.nqueues = P->nqueues;
         rp.out_mask = a->out_mask;
-        if ((e = launch_hrms1d(a->variant, a->dtype, shape, rp, P->grid, stream)) != hipSuccess)
+        if (!P->tiles.empty() &&
+            (e = launch_hrms1d(a->variant, a->dtype, shape, rp, P->grid, stream)) != hipSuccess)
             return e;
+        if (!P->tiles_top.empty()) {
+            rp.tiles = (const TileRec*)P->d_tiles_top.p;
+            rp.qbeg = (const int32_t*)P->d_qbeg_top.p;
+            rp.counters = (unsigned int*)P->d_counter.p + kMaxQueues;
+            if ((e = launch_hrms1d(a->variant, a->dtype, kTopShape, rp, P->grid_top, stream)) !=
+                hipSuccess)
+                return e;
+        }
     }
     return hipSuccess;
 }
@@ -872,8 +930,8 @@ int hrms_autotune_1d(hrms_handle h, const hrms_run1d_args* a, void* hip_stream, 
     hipError_t e = hipSetDevice(h->device);
     if (e != hipSuccess) return hip_fail(h, e, "hipSetDevice");
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
-    Shape1D shapes[16];
-    const int ns = std::min(16, hrms1d_shapes(a->variant, shapes, 16));
+    Shape1D shapes[32];
+    const int ns = std::min(32, hrms1d_shapes(a->variant, shapes, 32));
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
         if (e0) (void)hipEventDestroy(e0);
@@ -910,6 +968,7 @@ int hrms_autotune_1d(hrms_handle h, const hrms_run1d_args* a, void* hip_stream, 
         chosen[0] = shapes[best].wg;
         chosen[1] = shapes[best].r;
         chosen[2] = shapes[best].chunk;
+        chosen[3] = shapes[best].top;
     }
     if (!h->tune_path.empty()) save_tune(h);
     return HRMS_OK;

@@ -23,12 +23,12 @@ struct LevelConst {
 // queue w % nqueues, claims its tiles through the queue's atomic counter and
 // moves on to the following queues once its own is drained.
 constexpr int kMaxQueues = 8;
+constexpr int kCounterSlots = 2 * kMaxQueues;   // main launch, top-band launch
 
 struct Run1DParams {
     const void* x;
     const SpecDesc* spec;
     const TileRec* tiles;       // queue q holds tiles[qbeg[q] .. qbeg[q + 1])
-    const PieceRec* pieces;
     const LevelConst* consts;   // [n_spec][kMaxLevels]
     float* h;
     float* max_snr;
@@ -100,17 +100,29 @@ struct QuantParams {
 // Launch shapes of the 1D harmonic-sum kernel family.
 struct Shape1D {
     int wg;        // threads per workgroup
-    int r;         // outputs per thread (tile = wg * r outputs)
-    int chunk;     // LDS staging buffer in bins (one of two); Max and Greedy
-                   // keep the last 32 for the window past the chunk
+    int r;         // outputs per thread
+    int chunk;     // eq. (2)-(4): positions per LDS chunk (two are kept); 0: gathered
+                   // from global memory (and eq. (1))
+    int top;       // eq. (2)-(4): bands whose top level is at least `top` run in a
+                   // second launch of the LDS form with kTopShape; 0: none
 };
+
+// Launch shape of the LDS form for the top bands of a split launch.
+constexpr Shape1D kTopShape{1024, 8, 16384, 0};
 
 // Kernel launchers (hrms_kernels.hip). Return hipSuccess or the launch error.
 hipError_t launch_stats_partial(int dtype, const StatsParams& p, hipStream_t s);
 hipError_t launch_consts(const ConstsParams& p, hipStream_t s);
 hipError_t launch_hrms1d(int variant, int dtype, const Shape1D& shape, const Run1DParams& p,
                          int grid, hipStream_t s);
-int hrms1d_max_blocks_per_cu(int variant, int dtype, const Shape1D& shape);
+// Outputs per tile of a launch shape: every thread holds r outputs.
+inline int hrms1d_tile_outputs(int variant, const Shape1D& s)
+{
+    (void)variant;
+    return s.wg * s.r;
+}
+// Resident workgroups per CU of the 1D kernel; 0 (with *err set) on failure.
+int hrms1d_max_blocks_per_cu(int variant, int dtype, const Shape1D& shape, hipError_t* err);
 bool hrms1d_shape_supported(int variant, const Shape1D& shape);
 // Shapes compiled for the variant's kernel family; returns their count and
 // writes up to `cap` of them.

@@ -4,30 +4,33 @@
 // algorithm" (arXiv:1812.02647); eq. (1) in Sec. 1, eq. (2)-(4) in Sec. 2.
 //
 // Design (memory-bound; no matrix cores):
-//   * A tile is T = WG * R consecutive outputs [a, a + T) of one spectrum; thread
-//     t owns outputs a + r * WG + t, r < R, and keeps their running sums, best
-//     SNR and best level (and Greedy's offset j) in registers.
-//   * Harmonic i of the tile reads the contiguous span [i a, i (a + T)) (plus up
-//     to i - 1 bins of window). The tile streams the union of these spans
-//     through LDS in chunks of C bins (+ a 32-bin halo for the windows of
-//     eq. (2) and (4)), loaded with 16-byte coalesced loads, so the stride-i
-//     gather of eq. (2)-(4) never reaches HBM or L2 directly. Spans of
-//     neighbouring harmonics overlap once i T >= a, and are then staged once.
-//   * Position i n of output n lies in exactly one chunk, chunks are visited in
-//     increasing position and harmonics in increasing i inside a chunk, so every
-//     output adds its harmonics in the order i = 1..H of the equations.
-//   * A level snapshot (h = S * fl32(1/sqrt(H)), SNR, best level) is taken when
-//     i reaches a power of two.
-//   * LDS holds FP32 whatever the storage type; a 1-in-32 padding keeps strided
-//     reads (stride i) nearly free of bank conflicts.
-//   * The grid is persistent: workgroups pull tiles from a cost-sorted list
-//     through one atomic counter (the paper's load-balancing concern, Sec. 1).
+//   * eq. (2)-(4): a tile is a run of outputs of one band (outputs with the
+//     same top level). Harmonic i of the tile reads a contiguous span of
+//     positions; the tile streams the union of its spans through LDS in
+//     chunks loaded with 16-byte coalesced loads, so the stride-i gather never
+//     reaches HBM or L2 directly and a position read by several harmonics of
+//     the tile is staged once. Running sums, best SNR and best level live in
+//     LDS, one slot per output of the tile.
+//   * Every output adds its harmonics in the order i = 1..H of the equations
+//     (chunks in increasing position, harmonics in increasing i inside a
+//     chunk, one thread per output); a level snapshot
+//     (h = S * fl32(1/sqrt(H)), SNR, best level) is taken when i reaches a
+//     power of two.
+//   * eq. (1): every term of every level is one of Hmax bins
+//     x[round(n k / Hmax)]; they are read straight from global memory with
+//     coalesced buffer loads.
+//   * LDS holds FP32 whatever the storage type; a 1-in-32 padding keeps
+//     strided reads (stride i) nearly free of bank conflicts.
+//   * The grids are persistent: workgroups pull tiles from per-XCD queues of
+//     cost-sorted tiles through atomic counters (the paper's load-balancing
+//     concern, Sec. 1).
 #include <hip/hip_runtime.h>
 
 #include <climits>
 #include <cstdint>
 
 #include "hrms_internal.h"
+#include "hrms_plan.h"
 
 namespace hrms {
 namespace {
@@ -57,41 +60,6 @@ __device__ __forceinline__ float load_scalar(const void* base, int64_t idx)
         return h2f(static_cast<const uint16_t*>(base)[idx]);
     } else {
         return bf2f(static_cast<const uint16_t*>(base)[idx]);
-    }
-}
-
-// Loads the kVec elements starting at absolute element index `abs` (a multiple
-// of kVec); elements outside [lo, hi) read as 0.
-template <int DT>
-__device__ __forceinline__ void load_vec(const void* base, int64_t abs, int64_t lo, int64_t hi,
-                                         float (&v)[Elem<DT>::kVec])
-{
-    constexpr int V = Elem<DT>::kVec;
-    if (abs >= lo && abs + V <= hi) {
-        const uint4 u = *reinterpret_cast<const uint4*>(static_cast<const char*>(base) +
-                                                        abs * Elem<DT>::kBytes);
-        const uint32_t w[4] = {u.x, u.y, u.z, u.w};
-        if constexpr (DT == kF32) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) v[e] = __uint_as_float(w[e]);
-        } else {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                if constexpr (DT == kF16) {
-                    v[2 * e] = h2f(w[e] & 0xffffu);
-                    v[2 * e + 1] = h2f(w[e] >> 16);
-                } else {
-                    v[2 * e] = bf2f(w[e] & 0xffffu);
-                    v[2 * e + 1] = bf2f(w[e] >> 16);
-                }
-            }
-        }
-    } else {
-#pragma unroll
-        for (int e = 0; e < V; ++e) {
-            const int64_t k = abs + e;
-            v[e] = (k >= lo && k < hi) ? load_scalar<DT>(base, k) : 0.0f;
-        }
     }
 }
 
@@ -128,68 +96,60 @@ __device__ __forceinline__ int align_chunk(int64_t xoff, int p)
     return p - (int)((xoff + p) & (V - 1));
 }
 
-// Raw 16-byte vector of the input (kVec elements) with zeros outside [lo, hi).
-template <int DT>
-__device__ __forceinline__ uint4 load_raw(const void* base, int64_t abs, int64_t lo, int64_t hi)
-{
-    constexpr int V = Elem<DT>::kVec;
-    if (abs >= lo && abs + V <= hi)
-        return *reinterpret_cast<const uint4*>(static_cast<const char*>(base) +
-                                               abs * Elem<DT>::kBytes);
-    uint32_t w[4] = {0u, 0u, 0u, 0u};
-#pragma unroll
-    for (int e = 0; e < V; ++e) {
-        const int64_t k = abs + e;
-        if (k >= lo && k < hi) {
-            if constexpr (DT == kF32) {
-                w[e] = static_cast<const uint32_t*>(base)[k];
-            } else {
-                const uint32_t b = static_cast<const uint16_t*>(base)[k];
-                w[e >> 1] |= b << (16 * (e & 1));
-            }
-        }
-    }
-    return uint4{w[0], w[1], w[2], w[3]};
-}
-
-template <int DT>
-__device__ __forceinline__ void store_raw(float* buf, int k0, const uint4& u)
-{
-    const uint32_t w[4] = {u.x, u.y, u.z, u.w};
-    if constexpr (DT == kF32) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) buf[pidx(k0 + e)] = __uint_as_float(w[e]);
-    } else {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const float lo = DT == kF16 ? h2f(w[e] & 0xffffu) : bf2f(w[e] & 0xffffu);
-            const float hi = DT == kF16 ? h2f(w[e] >> 16) : bf2f(w[e] >> 16);
-            buf[pidx(k0 + 2 * e)] = lo;
-            buf[pidx(k0 + 2 * e + 1)] = hi;
-        }
-    }
-}
-
 // Register stage of one chunk: VPT 16-byte vectors per thread.
+//
+// Vector vi holds positions p0 + vi V .. + V - 1 of a spectrum whose first bin
+// is x[xoff]; p0 is 16-byte aligned in the batch. Positions outside the
+// spectrum are never read by a term, so a vector that lies wholly outside it
+// is replaced by the spectrum's nearest vector: every load stays inside the
+// batch. (A vector holding any element of the batch lies inside the batch's
+// last 16-byte block at worst, which x's 16-byte alignment keeps mapped.)
 template <int DT, int WG, int VPT>
 struct Stage {
     uint4 v[VPT];
     __device__ __forceinline__ void load(const void* x, int64_t xoff, int n_bins, int p0, int nvec)
     {
         constexpr int V = Elem<DT>::kVec;
+        constexpr int B = Elem<DT>::kBytes;
+        // element offsets relative to the spectrum's first 16-byte boundary
+        const int64_t first = xoff & ~(int64_t)(V - 1);
+        const int last = (int)(((xoff + n_bins - 1) & ~(int64_t)(V - 1)) - first);
+        const char* base = static_cast<const char*>(x) + first * B;
+        const int rel0 = (int)(xoff - first) + p0;
 #pragma unroll
         for (int u = 0; u < VPT; ++u) {
             const int vi = u * WG + (int)threadIdx.x;
-            if (vi < nvec) v[u] = load_raw<DT>(x, xoff + p0 + (int64_t)vi * V, xoff, xoff + n_bins);
+            if (vi < nvec) {
+                int e = rel0 + vi * V;
+                e = e < 0 ? 0 : e > last ? last : e;
+                v[u] = *reinterpret_cast<const uint4*>(base + e * B);
+            }
         }
     }
     __device__ __forceinline__ void store(float* buf, int nvec) const
     {
         constexpr int V = Elem<DT>::kVec;
+        constexpr int STEP = WG * V;   // chunk positions per vector slot u
+        static_assert(STEP % 32 == 0, "a vector slot spans whole padding blocks");
+        // pidx(k0 + u STEP + e) = pidx(k0) + u (STEP + STEP / 32) + e for e < V
+        float* b = buf + pidx((int)threadIdx.x * V);
 #pragma unroll
         for (int u = 0; u < VPT; ++u) {
             const int vi = u * WG + (int)threadIdx.x;
-            if (vi < nvec) store_raw<DT>(buf, vi * V, v[u]);
+            if (vi < nvec) {
+                float* d = b + u * (STEP + STEP / 32);
+                const uint32_t w[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+                if constexpr (DT == kF32) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) d[e] = __uint_as_float(w[e]);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        d[2 * e] = DT == kF16 ? h2f(w[e] & 0xffffu) : bf2f(w[e] & 0xffffu);
+                        d[2 * e + 1] = DT == kF16 ? h2f(w[e] >> 16) : bf2f(w[e] >> 16);
+                    }
+                }
+            }
         }
     }
 };
@@ -212,57 +172,156 @@ __device__ __forceinline__ int claim_tile(const Run1DParams& p, int& q, int& vis
 // --------------------------------------------------------------------------
 // eq. (2)-(4): outputs indexed by the fundamental.
 //
-// A tile is the T = WG * R outputs [a, aend) of one spectrum; thread t holds
-// outputs a + r WG + t (r < R) in registers: running sum, best SNR, best level
-// and Greedy's offset j. Harmonic i is needed for the outputs
-// n < floor(N / 2^level(i)) and reads positions i n (+ up to i - 1 bins of
-// window for eq. (2) and (4)).
+// A tile is a run [a, aend) of at most T = WG * R outputs of one band (all of
+// its outputs have the same top level Ht = 2^(nlev - 1)); thread t holds
+// outputs a + r WG + t (r < R) in registers: running sum, best SNR, best
+// level and Greedy's offset j. The tile walks the union of its harmonic spans
+// in chunks of at most CB positions (hrms_plan.h): a position that several
+// harmonics of the tile read is staged once, and a chunk serves the terms
+// whose window ends inside it -- for each harmonic i, a run of outputs. The
+// chunk's harmonics are visited in increasing i, chunks in increasing
+// position, so every output adds its terms in the order i = 1..H of the
+// equations; a level snapshot (h = S * fl32(1/sqrt(H)), SNR, best level) is
+// taken when i is a power of two, and max-SNR / best-H are written at i = Ht.
 //
-// The tile walks harmonic-major through a list of pieces built on the host:
-// piece (i, [n0, n1)) stages the bins i n0 .. i (n1 - 1) + window, which fit
-// one LDS buffer, and every output of the piece then adds its term. Each
-// output thus adds its harmonics in the order i = 1..H of the equations; a
-// level snapshot is taken when i is a power of two.
-//
-// Workgroup w serves the tiles of queue q = w % nq with stride G = grid / nq.
-// The next piece -- of this tile or of the next one -- is loaded into
-// registers while the current one is computed.
+// Chunks go global -> registers -> LDS through a double-buffered LDS chunk:
+// while chunk k is computed, chunk k + 1 sits in LDS and chunk k + 2 is in
+// flight to registers; one barrier per chunk. The grid is persistent: tiles
+// come from per-XCD queues of cost-sorted tiles, claimed one tile ahead.
 // --------------------------------------------------------------------------
+
+// One chunk of a tile, as the kernel carries it.
+struct ChunkDesc {
+    TileRec t;
+    int cp, ce, cep;   // chunk [cp, ce); cep: end of the previous chunk of the tile (0: first)
+};
+
+// Walks the chunks of the tiles claimed by the workgroup, in order. Tile c of
+// the workgroup is named by ring[c & 1]: thread 0 claims tile c + 1 when the
+// walk enters tile c. With one call of next per barrier phase, tile c was
+// claimed at least one barrier before it is read, and its slot is rewritten
+// (with tile c + 2) at least one barrier after every wave has read it.
+template <int DT, int CB, int WIN>
+struct ChunkCursor {
+    TileRec t;
+    SpanWalk w;
+    int seq;
+    bool live;
+
+    __device__ __forceinline__ void open()
+    {
+        constexpr int V = Elem<DT>::kVec;
+        w.begin(t.a, t.aend, 1 << (t.nlev - 1), WIN, V, CB, (int)(t.xoff & (V - 1)));
+    }
+    __device__ __forceinline__ void start(const Run1DParams& p, const int* ring)
+    {
+        seq = 0;
+        const int id = uniform(ring[0]);
+        live = id >= 0;
+        if (live) {
+            t = ldc(p.tiles + id);
+            open();
+        }
+    }
+    __device__ __forceinline__ bool next(const Run1DParams& p, int* ring, int& cq, int& visited,
+                                         ChunkDesc& d)
+    {
+        if (!live) return false;
+        if (!w.next(d.cp, d.ce, d.cep)) {
+            ++seq;
+            const int id = uniform(ring[seq & 1]);
+            if (id < 0) {
+                live = false;
+                return false;
+            }
+            if (threadIdx.x == 0) ring[(seq + 1) & 1] = claim_tile(p, cq, visited);
+            t = ldc(p.tiles + id);
+            open();
+            w.next(d.cp, d.ce, d.cep);
+        }
+        d.t = t;
+        return true;
+    }
+};
+
+// Term i of an output whose window starts at chunk position k (LDS index
+// idx = pidx(k)). Greedy reads its offset j from st (bits 8..) and sets
+// step when the right neighbour is taken (j then grows by one).
+template <int VAR>
+__device__ __forceinline__ float term_value(const float* buf, int k, int idx, int i, int st,
+                                            bool& step)
+{
+    step = false;
+    if constexpr (VAR == kFreqbin) {
+        return buf[idx];
+    } else if constexpr (VAR == kMax) {
+        float tv = buf[idx];
+        for (int jj = 1; jj < i; ++jj) {
+            const float w = buf[pidx(k + jj)];
+            tv = w > tv ? w : tv;
+        }
+        return tv;
+    } else {
+        if (i == 1) return buf[idx];
+        const int j = st >> 8;
+        const float x0 = buf[pidx(k + j)];
+        const float x1 = buf[pidx(k + j + 1)];
+        step = x1 > x0;
+        return step ? x1 : x0;
+    }
+}
+
+constexpr int kBufferFlags = 0x00020000;   // raw (untyped) 32-bit buffer, gfx9 word 3
+
+// Raw buffer over [base, base + bytes): a store past the end is dropped.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t out_rsrc(const void* base, int bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes,
+                                             kBufferFlags);
+}
+
 template <int VAR, int DT, int WG, int R, int CB>
-__global__ __launch_bounds__(WG) void k_hrms1d_fund(const Run1DParams p)
+__global__ __launch_bounds__(WG) void k_hrms1d_span(const Run1DParams p)
 {
     constexpr int V = Elem<DT>::kVec;
     static_assert(CB % V == 0, "chunk must be a multiple of the vector");
+    static_assert((WG & (WG - 1)) == 0 && WG >= 64, "WG must be a power of two");
     constexpr int NVEC = CB / V;
     constexpr int VPT = (NVEC + WG - 1) / WG;
     constexpr int BUF = VPT * WG * V;
-    constexpr int T = WG * R;
-    static_assert((WG & (WG - 1)) == 0, "WG must be a power of two");
-    static_assert(T <= 0xffff, "tile offsets are 16-bit");
-    constexpr int WSH = __builtin_ctz(WG);
-    __shared__ float lds[BUF + (BUF >> 5) + 1];
+    constexpr int LDSB = BUF + (BUF >> 5) + 1;
+    constexpr int WIN = VAR == kFreqbin ? 0 : 1;
+    constexpr int TSH = __builtin_ctz(WG);
+    __shared__ float lds[2][LDSB];
+    __shared__ int ring[2];
 
     const int tid = (int)threadIdx.x;
-    // Tile claims run two tiles ahead of use: s_claim[c & 1] is written when
-    // tile c - 1 starts and read when tile c starts.
-    __shared__ int s_claim[3];
+    const int lane = tid & 63;
+    const int wbase = uniform(tid & ~63);   // first thread of this wave
+    const bool track = (p.out_mask & 6u) != 0;
     int cq = (int)(blockIdx.x % (unsigned)p.nqueues), visited = 0;
     if (tid == 0) {
-        s_claim[2] = claim_tile(p, cq, visited);   // tile 0
-        s_claim[1] = claim_tile(p, cq, visited);   // tile 1
-        s_claim[0] = claim_tile(p, cq, visited);   // tile 2
+        ring[0] = claim_tile(p, cq, visited);
+        ring[1] = claim_tile(p, cq, visited);
     }
     __syncthreads();
-    int t = uniform(s_claim[2]);
-    if (t < 0) return;
-    int tn = uniform(s_claim[1]);
-    int c = 1;   // index of the tile that tn names
 
-    TileRec ct = ldc(p.tiles + t);
-    int pi = ct.pbeg, pe = ct.pbeg + ct.pcount;
-    PieceRec cp = ldc(p.pieces + pi);
-    TileRec ft = ct;   // record of tile tn, fetched a whole tile ahead of its use
-    if (tn >= 0) ft = ldc(p.tiles + tn);
+    // Every call of g.next sits in a barrier phase of its own, so that a
+    // ring slot is read by all waves before it is rewritten and rewritten
+    // before it is read again.
+    ChunkCursor<DT, CB, WIN> g;
+    g.start(p, ring);
+    Stage<DT, WG, VPT> stage;
+    ChunkDesc d0, d1, d2;
+    bool h0 = g.next(p, ring, cq, visited, d0);
+    if (h0) {
+        stage.load(p.x, d0.t.xoff, d0.t.n, d0.cp, (d0.ce - d0.cp + V - 1) / V);
+        stage.store(lds[0], (d0.ce - d0.cp + V - 1) / V);
+    }
+    __syncthreads();
+    bool h1 = h0 && g.next(p, ring, cq, visited, d1);
+    if (h1) stage.load(p.x, d1.t.xoff, d1.t.n, d1.cp, (d1.ce - d1.cp + V - 1) / V);
+    __syncthreads();   // chunk 0 is in LDS
 
     float acc[R], best[R];
     int st[R];   // best level (bits 0..7) | Greedy offset j (bits 8..)
@@ -272,117 +331,146 @@ __global__ __launch_bounds__(WG) void k_hrms1d_fund(const Run1DParams p)
         best[r] = 0.0f;
         st[r] = 0;
     }
+    // constants of the current spectrum, lane l holding level l
+    float lm = 0.0f, lq = 0.0f, lrh = 0.0f;
+    int lho_lo = 0, lho_hi = 0;
+    int cur_spec = -1;
 
-    Stage<DT, WG, VPT> stage;
-    stage.load(p.x, ct.xoff, ct.n, cp.p0, cp.nv);
-    stage.store(lds, cp.nv);
-    __syncthreads();
-    for (;;) {
-        // next piece: of this tile, else the first of the following tile
-        const bool newtile = pi + 1 >= pe;
-        const bool more = !newtile || tn >= 0;
-        const TileRec& nt = newtile ? ft : ct;
-        PieceRec np = cp;
-        if (more) {
-            np = ldc(p.pieces + (newtile ? nt.pbeg : pi + 1));
-            stage.load(p.x, nt.xoff, nt.n, np.p0, np.nv);
-        }
+    for (int k = 0; h0; ++k) {
+        // chunk k + 1 -> LDS (its buffer held chunk k - 1), chunk k + 2 -> registers
+        if (h1) stage.store(lds[(k + 1) & 1], (d1.ce - d1.cp + V - 1) / V);
+        const bool h2 = h1 && g.next(p, ring, cq, visited, d2);
+        if (h2) stage.load(p.x, d2.t.xoff, d2.t.n, d2.cp, (d2.ce - d2.cp + V - 1) / V);
 
-        // this piece
-        {
-            const int a = ct.a;
-            const int i = cp.ih & 0xff;
-            const int li = (cp.ih >> 8) & 0xff;
-            const bool snap = (cp.ih >> 16) & 1;
-            const int n0 = a + (cp.nr & 0xffff), n1 = a + (cp.nr >> 16);
-            const int p0 = cp.p0;
-            float m = 0.0f, qq = 0.0f, rh = 0.0f;
-            int64_t ho = 0;
-            if (snap) {
-                const LevelConst c = ldc(p.consts + (int64_t)ct.spec * kMaxLevels + li);
-                m = c.m;
-                qq = c.q;
-                rh = c.rh;
-                ho = ldc(p.spec[ct.spec].hoff + li);
-            }
-            const int r0 = (n0 - a) >> WSH, r1 = (n1 - 1 - a) >> WSH;
+        // ---- chunk k ----
+        const float* buf = lds[k & 1];
+        const int a = d0.t.a;
+        const int ht = 1 << (d0.t.nlev - 1);
+        if (d0.cep == 0) {
+            // first chunk of a tile: fresh outputs (Greedy starts from -0 so
+            // that its first term passes unchanged, the others from +0)
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                if (r >= r0 && r <= r1) {
-                    const int n = a + (r << WSH) + tid;
-                    if (n >= n0 && n < n1) {
-                        const int k = i * n - p0;
-                        float tv;
-                        if constexpr (VAR == kFreqbin) {
-                            tv = lds[pidx(k)];
-                        } else if constexpr (VAR == kMax) {
-                            tv = lds[pidx(k)];
-                            for (int jj = 1; jj < i; ++jj) {
-                                const float w = lds[pidx(k + jj)];
-                                tv = w > tv ? w : tv;
-                            }
-                        } else {
-                            if (i == 1) {
-                                tv = lds[pidx(k)];
-                            } else {
-                                const int j = st[r] >> 8;
-                                const float x0 = lds[pidx(k + j)];
-                                const float x1 = lds[pidx(k + j + 1)];
-                                if (x1 > x0) {
-                                    tv = x1;
-                                    st[r] += 256;
-                                } else {
-                                    tv = x0;
-                                }
-                            }
+                acc[r] = VAR == kGreedy ? -0.0f : 0.0f;
+                st[r] = 0;
+            }
+            if (d0.t.spec != cur_spec) {
+                cur_spec = d0.t.spec;
+                if (lane < kMaxLevels) {
+                    const LevelConst lc = p.consts[(int64_t)cur_spec * kMaxLevels + lane];
+                    lm = lc.m;
+                    lq = lc.q;
+                    lrh = lc.rh;
+                    const int64_t ho = p.spec[cur_spec].hoff[lane];
+                    lho_lo = (int)(uint32_t)ho;
+                    lho_hi = (int)(ho >> 32);
+                }
+            }
+        }
+        const int tn = d0.t.aend - a;   // outputs of the tile
+        int nbv = 0, nev = 0;
+        if (lane < ht) chunk_terms(lane + 1, WIN * lane, d0.cep, d0.ce, a, d0.t.aend, nbv, nev);
+        uint32_t segs = (uint32_t)__ballot(lane < ht && nbv < nev);
+        while (segs) {
+            const int l = __builtin_ctz(segs);
+            segs &= segs - 1;
+            const int i = l + 1;
+            // outputs [a + ub, a + ue) take term i from this chunk
+            const int ub = __builtin_amdgcn_readlane(nbv, l) - a;
+            const int ue = __builtin_amdgcn_readlane(nev, l) - a;
+            // this wave's output blocks [r WG + wbase, + 64) that meet [ub, ue)
+            const int lo = ub - wbase - 63, hi = ue - 1 - wbase;
+            const int r_lo = lo <= 0 ? 0 : (lo + WG - 1) >> TSH;
+            const int r_hi = hi < 0 ? -1 : (hi >> TSH) < R - 1 ? (hi >> TSH) : R - 1;
+            if (r_lo > r_hi) continue;
+            // every lane of every block inside the run: no per-lane checks
+            const bool full = r_lo == 0 && r_hi == R - 1 && ub <= wbase &&
+                              ue >= (R - 1) * WG + wbase + 64;
+            // chunk position of term i of output a + r WG + tid: k0 + r i WG;
+            // i WG is a multiple of 32, so its LDS index is pidx(k0) + r rstep
+            const int k0 = (int)__umul24((unsigned)i, (unsigned)tid) + i * a - d0.cp;
+            const int rstep = i * (WG + WG / 32);
+            const int x0 = pidx(k0);
+            const int span = ue - ub;
+            const int u0 = tid - ub;   // output offset in the run, block 0
+            const bool snap = (i & (i - 1)) == 0;
+            if (!snap) {
+                if (full) {
+                    float tv[R];
+                    bool stp[R];
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        tv[r] = term_value<VAR>(buf, k0 + r * i * WG, x0 + r * rstep, i, st[r],
+                                                stp[r]);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        acc[r] = acc[r] + tv[r];
+                        if (stp[r]) st[r] += 256;
+                    }
+                } else {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        if (r < r_lo || r > r_hi) continue;
+                        if ((unsigned)(u0 + r * WG) < (unsigned)span) {
+                            bool stp;
+                            const float tv = term_value<VAR>(buf, k0 + r * i * WG, x0 + r * rstep,
+                                                             i, st[r], stp);
+                            acc[r] = acc[r] + tv;
+                            if (stp) st[r] += 256;
                         }
-                        acc[r] = acc[r] + tv;
-                        if (snap) {
-                            const float hv = acc[r] * rh;
-                            if (p.out_mask & 1u) p.h[ho + n] = hv;
-                            const float snr = (hv - m) * qq;
-                            if (li == 0 || snr > best[r]) {
-                                best[r] = snr;
-                                st[r] = (st[r] & ~255) | li;
-                            }
+                    }
+                }
+                continue;
+            }
+            // snapshot harmonic (i = 2^li)
+            const int li = __builtin_ctz((unsigned)i);
+            const float rh = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lrh), li));
+            const float m0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lm), li));
+            const float q0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lq), li));
+            const int64_t ho =
+                (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane(lho_hi, li) << 32) |
+                          (uint32_t)__builtin_amdgcn_readlane(lho_lo, li));
+            const bool fin = i == ht;
+            // the tile's outputs in each output array; block r at byte r WG size
+            const __amdgpu_buffer_rsrc_t hrs = out_rsrc(p.h + ho + a, tn * 4);
+            const __amdgpu_buffer_rsrc_t mrs = out_rsrc(p.max_snr + d0.t.xoff + a, tn * 4);
+            const __amdgpu_buffer_rsrc_t brs = out_rsrc(p.best_h + d0.t.xoff + a, tn);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (r < r_lo || r > r_hi) continue;
+                if (full || (unsigned)(u0 + r * WG) < (unsigned)span) {
+                    bool stp;
+                    const float tv = term_value<VAR>(buf, k0 + r * i * WG, x0 + r * rstep, i,
+                                                     st[r], stp);
+                    if (stp) st[r] += 256;
+                    acc[r] = acc[r] + tv;
+                    const float hv = acc[r] * rh;
+                    if (p.out_mask & 1u)
+                        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(hv), hrs, tid * 4,
+                                                              r * WG * 4, 0);
+                    if (track) {
+                        const float snr = (hv - m0) * q0;
+                        if (li == 0 || snr > best[r]) {
+                            best[r] = snr;
+                            st[r] = (st[r] & ~255) | li;
+                        }
+                        if (fin) {
+                            if (p.out_mask & 2u)
+                                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(best[r]), mrs,
+                                                                      tid * 4, r * WG * 4, 0);
+                            if (p.out_mask & 4u)
+                                __builtin_amdgcn_raw_buffer_store_b8(
+                                    (uint8_t)(1u << (st[r] & 255)), brs, tid, r * WG, 0);
                         }
                     }
                 }
             }
         }
-
-        if (newtile) {
-            const int a = ct.a;
-            const int aend = min(a + T, ct.n);
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int n = a + (r << WSH) + tid;
-                if (n < aend) {
-                    if (p.out_mask & 2u) p.max_snr[ct.xoff + n] = best[r];
-                    if (p.out_mask & 4u) p.best_h[ct.xoff + n] = (uint8_t)(1u << (st[r] & 255));
-                }
-                acc[r] = 0.0f;
-                best[r] = 0.0f;
-                st[r] = 0;
-            }
-        }
-        if (!more) break;
-        __syncthreads();   // every thread is done with this piece
-        stage.store(lds, np.nv);
-        __syncthreads();
-        if (newtile) {
-            t = tn;
-            ct = ft;
-            pe = ct.pbeg + ct.pcount;
-            pi = ct.pbeg;
-            ++c;
-            tn = uniform(s_claim[c & 1]);
-            if (tid == 0) s_claim[(c + 1) & 1] = claim_tile(p, cq, visited);
-            if (tn >= 0) ft = ldc(p.tiles + tn);
-        } else {
-            ++pi;
-        }
-        cp = np;
+        __syncthreads();   // chunk k done; chunk k + 1 visible
+        d0 = d1;
+        h0 = h1;
+        d1 = d2;
+        h1 = h2;
     }
 }
 
@@ -411,12 +499,10 @@ __device__ __forceinline__ float buffer_elem(__amdgpu_buffer_rsrc_t rs, int pos)
     }
 }
 
-constexpr int kBufferFlags = 0x00020000;   // raw (untyped) 32-bit buffer, gfx9 word 3
 
 template <int DT, int WG, int R, int CB>
 __global__ __launch_bounds__(WG) void k_hrms1d_eq1(const Run1DParams p)
 {
-    constexpr int T = WG * R;
     const int tid = (int)threadIdx.x;
     __shared__ int s_claim[2];
     int cq = (int)(blockIdx.x % (unsigned)p.nqueues), visited = 0;
@@ -430,7 +516,7 @@ __global__ __launch_bounds__(WG) void k_hrms1d_eq1(const Run1DParams p)
         const int a = ct.a;
         const int N = ct.n;
         const int nl = ct.nlev;
-        const int aend = min(a + T, N);
+        const int aend = ct.aend;
         const int sh = nl - 1;
         const int Lh = 1 << sh;
         const unsigned half = (unsigned)Lh >> 1;
@@ -497,6 +583,149 @@ __global__ __launch_bounds__(WG) void k_hrms1d_eq1(const Run1DParams p)
             if (act[r]) {
                 if (p.out_mask & 2u) p.max_snr[ct.xoff + nn[r]] = best[r];
                 if (p.out_mask & 4u) p.best_h[ct.xoff + nn[r]] = (uint8_t)(1u << bl[r]);
+            }
+        }
+        __syncthreads();
+        t = uniform(s_claim[(c + 1) & 1]);
+    }
+}
+
+// --------------------------------------------------------------------------
+// eq. (2)-(4), gathered straight from global memory: a tile is a run of at
+// most T = WG * R outputs of one band; thread t holds outputs a + r WG + t in
+// registers and, for i = 1..Ht in turn, loads the bins of term i of all R
+// outputs at once (positions i n, stepped by n from harmonic to harmonic) with
+// 32-bit-offset buffer loads over the spectrum. Neighbouring outputs read
+// positions i apart, so a wavefront's load covers about 2i cache lines that
+// the other harmonics of other tiles read as well (the L2 and the
+// memory-side cache serve the reuse). Each output adds its terms in the
+// order i = 1..H; snapshots as in the LDS form.
+// --------------------------------------------------------------------------
+template <int VAR, int DT, int WG, int R>
+__global__ __launch_bounds__(WG) void k_hrms1d_gather(const Run1DParams p)
+{
+    const int tid = (int)threadIdx.x;
+    const int lane = tid & 63;
+    const bool track = (p.out_mask & 6u) != 0;
+    __shared__ int s_claim[2];
+    int cq = (int)(blockIdx.x % (unsigned)p.nqueues), visited = 0;
+    if (tid == 0) s_claim[0] = claim_tile(p, cq, visited);
+    __syncthreads();
+    int t = uniform(s_claim[0]);
+    int cur_spec = -1;
+    float lm = 0.0f, lq = 0.0f, lrh = 0.0f;
+    int lho_lo = 0, lho_hi = 0;
+    for (int c = 0; t >= 0; ++c) {
+        // claim the following tile now; it is read after this tile's barrier
+        if (tid == 0) s_claim[(c + 1) & 1] = claim_tile(p, cq, visited);
+        const TileRec ct = ldc(p.tiles + t);
+        const int a = ct.a;
+        const int ht = 1 << (ct.nlev - 1);
+        const int tn = ct.aend - a;
+        if (ct.spec != cur_spec) {
+            cur_spec = ct.spec;
+            if (lane < kMaxLevels) {
+                const LevelConst lc = p.consts[(int64_t)cur_spec * kMaxLevels + lane];
+                lm = lc.m;
+                lq = lc.q;
+                lrh = lc.rh;
+                const int64_t ho = p.spec[cur_spec].hoff[lane];
+                lho_lo = (int)(uint32_t)ho;
+                lho_hi = (int)(ho >> 32);
+            }
+        }
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)(static_cast<const char*>(p.x) + ct.xoff * Elem<DT>::kBytes), (short)0,
+            ct.n * Elem<DT>::kBytes, kBufferFlags);
+        const __amdgpu_buffer_rsrc_t mrs = out_rsrc(p.max_snr + ct.xoff + a, tn * 4);
+        const __amdgpu_buffer_rsrc_t brs = out_rsrc(p.best_h + ct.xoff + a, tn);
+
+        float acc[R], best[R];
+        int st[R], pos[R], nn[R];
+        bool act[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int n = a + r * WG + tid;
+            act[r] = n < ct.aend;
+            nn[r] = act[r] ? n : a;
+            pos[r] = 0;
+            // Greedy starts from -0 so that its first term passes unchanged
+            acc[r] = VAR == kGreedy ? -0.0f : 0.0f;
+            best[r] = 0.0f;
+            st[r] = 0;
+        }
+        for (int i = 1; i <= ht; ++i) {
+            float tv[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) pos[r] += nn[r];
+            if constexpr (VAR == kFreqbin) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) tv[r] = buffer_elem<DT>(rs, pos[r]);
+            } else if constexpr (VAR == kMax) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) tv[r] = buffer_elem<DT>(rs, pos[r]);
+                for (int jj = 1; jj < i; ++jj) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const float w = buffer_elem<DT>(rs, pos[r] + jj);
+                        tv[r] = w > tv[r] ? w : tv[r];
+                    }
+                }
+            } else {
+                if (i == 1) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) tv[r] = buffer_elem<DT>(rs, pos[r]);
+                } else {
+                    float x0[R], x1[R];
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const int q = pos[r] + (st[r] >> 8);
+                        x0[r] = buffer_elem<DT>(rs, q);
+                        x1[r] = buffer_elem<DT>(rs, q + 1);
+                    }
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const bool step = x1[r] > x0[r];
+                        tv[r] = step ? x1[r] : x0[r];
+                        st[r] += step ? 256 : 0;
+                    }
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r] = acc[r] + tv[r];
+            if ((i & (i - 1)) == 0) {
+                const int li = __builtin_ctz((unsigned)i);
+                const float rh =
+                    __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lrh), li));
+                const float m0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lm), li));
+                const float q0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lq), li));
+                const int64_t ho =
+                    (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane(lho_hi, li) << 32) |
+                              (uint32_t)__builtin_amdgcn_readlane(lho_lo, li));
+                const __amdgpu_buffer_rsrc_t hrs = out_rsrc(p.h + ho + a, tn * 4);
+                const bool fin = i == ht;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const float hv = acc[r] * rh;
+                    const float snr = (hv - m0) * q0;
+                    if (li == 0 || snr > best[r]) {
+                        best[r] = snr;
+                        st[r] = (st[r] & ~255) | li;
+                    }
+                    if (act[r]) {
+                        if (p.out_mask & 1u)
+                            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(hv), hrs,
+                                                                  tid * 4, r * WG * 4, 0);
+                        if (fin && track) {
+                            if (p.out_mask & 2u)
+                                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(best[r]), mrs,
+                                                                      tid * 4, r * WG * 4, 0);
+                            if (p.out_mask & 4u)
+                                __builtin_amdgcn_raw_buffer_store_b8(
+                                    (uint8_t)(1u << (st[r] & 255)), brs, tid, r * WG, 0);
+                        }
+                    }
+                }
             }
         }
         __syncthreads();
@@ -597,7 +826,7 @@ __global__ __launch_bounds__(64) void k_consts(const ConstsParams p)
 {
     const int s = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (s == 0 && p.counters)
-        for (int q = 0; q < kMaxQueues; ++q) p.counters[q] = 0u;
+        for (int q = 0; q < kCounterSlots; ++q) p.counters[q] = 0u;
     if (s >= p.n_spec) return;
     const SpecDesc sd = p.spec[s];
     double mu, sigma;
@@ -779,7 +1008,10 @@ __global__ __launch_bounds__(kStatsWG) void k_quantize(const QuantParams p)
 template <int VAR, int DT, int WG, int R, int C>
 void* fund_kernel()
 {
-    return reinterpret_cast<void*>(&k_hrms1d_fund<VAR, DT, WG, R, C>);
+    if constexpr (C == 0)
+        return reinterpret_cast<void*>(&k_hrms1d_gather<VAR, DT, WG, R>);
+    else
+        return reinterpret_cast<void*>(&k_hrms1d_span<VAR, DT, WG, R, C>);
 }
 
 template <int DT, int WG, int R, int C>
@@ -821,11 +1053,12 @@ constexpr ShapeEntry eq1_shape()
 }
 
 const ShapeEntry kShapes[] = {
-    fund_shape<256, 8, 8192>(),
-    fund_shape<256, 8, 4096>(),
-    fund_shape<256, 16, 8192>(),
+    fund_shape<1024, 8, 16384>(),
+    fund_shape<1024, 16, 16384>(),
     fund_shape<512, 8, 8192>(),
-    fund_shape<128, 16, 8192>(),
+    fund_shape<256, 8, 0>(),
+    fund_shape<256, 16, 0>(),
+    fund_shape<512, 8, 0>(),
     eq1_shape<256, 8, 0>(),
     eq1_shape<256, 4, 0>(),
     eq1_shape<512, 8, 0>(),
@@ -870,28 +1103,54 @@ hipError_t launch_consts(const ConstsParams& p, hipStream_t s)
 
 bool hrms1d_shape_supported(int variant, const Shape1D& shape)
 {
+    if (shape.top != 0) {
+        // a split launch: eq. (2)-(4) only, at a power-of-two level
+        if (variant == kEq1 || shape.top < 2 || shape.top > 32 || (shape.top & (shape.top - 1)))
+            return false;
+    }
     return kernel_for(variant, kF32, shape) != nullptr;
 }
 
 int hrms1d_shapes(int variant, Shape1D* out, int cap)
 {
+    // every compiled shape; the gathered forms also split at the top band
     const int fam = variant == kEq1 ? 1 : 0;
     int n = 0;
     for (const ShapeEntry& e : kShapes) {
         if (e.eq1 != fam) continue;
-        if (out && n < cap) out[n] = Shape1D{e.wg, e.r, e.chunk};
+        if (out && n < cap) out[n] = Shape1D{e.wg, e.r, e.chunk, 0};
         ++n;
+        if (!fam && e.chunk == 0) {
+            if (out && n < cap) out[n] = Shape1D{e.wg, e.r, e.chunk, 32};
+            ++n;
+        }
     }
     return n;
 }
 
-int hrms1d_max_blocks_per_cu(int variant, int dtype, const Shape1D& shape)
+int hrms1d_max_blocks_per_cu(int variant, int dtype, const Shape1D& shape, hipError_t* err)
 {
+    if (err) *err = hipSuccess;
     void* k = kernel_for(variant, dtype, shape);
     if (!k) return 0;
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, shape.wg, 0) != hipSuccess) return 0;
-    return nb;
+    const hipError_t e1 = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, shape.wg, 0);
+    if (e1 == hipSuccess && nb > 0) return nb;
+    // The runtime's calculator declines some kernels with more than 64 KiB of
+    // LDS; count from the kernel's own resources instead: 160 KiB of LDS and
+    // 4 SIMDs of 512 VGPRs per lane (at most 8 waves each) per CU.
+    hipFuncAttributes fa{};
+    const hipError_t e2 = hipFuncGetAttributes(&fa, k);
+    if (e2 != hipSuccess) {
+        if (err) *err = e1 != hipSuccess ? e1 : e2;
+        return 0;
+    }
+    const int waves = (shape.wg + 63) / 64;
+    const int vgpr = fa.numRegs > 0 ? (fa.numRegs + 7) / 8 * 8 : 128;
+    const int per_simd = vgpr > 512 ? 0 : (512 / vgpr < 8 ? 512 / vgpr : 8);
+    const int by_waves = 4 * per_simd / waves;
+    const int by_lds = fa.sharedSizeBytes > 0 ? (int)(163840 / fa.sharedSizeBytes) : by_waves;
+    return by_waves < by_lds ? by_waves : by_lds;
 }
 
 hipError_t launch_hrms1d(int variant, int dtype, const Shape1D& shape, const Run1DParams& p,

@@ -18,24 +18,17 @@ struct SpecDesc {
     int32_t nlev;               // levels: log2(Hmax) + 1
 };
 
-// A tile of consecutive outputs [a, a + T) of one spectrum (1D kernels).
+// A tile of consecutive outputs [a, aend) of one spectrum (1D kernels). For
+// eq. (2)-(4) a tile lies inside one band and nlev is the band's level count;
+// for eq. (1) nlev is the spectrum's.
 struct TileRec {
     int64_t xoff;    // first bin of the spectrum in x (and in max_snr / best_h)
     int32_t n;       // bins of the spectrum
     int32_t a;       // first output of the tile
-    int32_t pbeg;    // first piece record of the tile (eq. (2)-(4))
-    int32_t pcount;  // piece records of the tile
+    int32_t aend;    // one past its last output
     int32_t spec;    // spectrum index (constants, h offsets)
-    int32_t nlev;    // levels of the spectrum
-};
-
-// One LDS piece of a tile (eq. (2)-(4)): harmonic i for the outputs
-// [a + n0r, a + n1r), staging the bins [p0, p0 + nv * 16 / sizeof(elem)).
-struct PieceRec {
-    int32_t p0;      // first staged bin, relative to the spectrum, 16-byte aligned in x
-    int32_t nr;      // n0r (bits 0..15) | n1r (bits 16..31)
-    int32_t ih;      // i (bits 0..7) | level(i) (bits 8..15) | snapshot flag (bit 16)
-    int32_t nv;      // 16-byte vectors to stage
+    int32_t nlev;    // levels of the tile's outputs
+    int32_t pad;
 };
 
 // A segment of one spectrum for the statistics reduction.

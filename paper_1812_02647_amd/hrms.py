@@ -182,8 +182,8 @@ def hrms_run_1d(handle, args: hrms_run1d_args, stream=None) -> None:
 
 def hrms_autotune_1d(handle, args: hrms_run1d_args, stream=None, reps: int = 3):
     """Times every compiled launch shape on this batch and keeps the fastest;
-    returns (wg, r, chunk)."""
-    chosen = (C.c_int32 * 3)()
+    returns (wg, r, chunk, top)."""
+    chosen = (C.c_int32 * 4)()
     _check(lib().hrms_autotune_1d(handle, C.byref(args), _stream_ptr(stream), reps, chosen),
            handle)
     return tuple(chosen)

@@ -72,7 +72,7 @@ def test_autotune_and_tune_cache(tmp_path):
             case_log(f"autotune variant={NAMES[v]}")
             b = H.Batch1D(xd, offsets, v, 32)
             shape = H.hrms_autotune_1d(h, b.args, reps=2)
-            assert all(s > 0 for s in shape[:2])
+            assert len(shape) == 4 and all(s > 0 for s in shape[:2])
             torch.cuda.synchronize()
             out = fetch(b)
             for s in range(6):
@@ -82,16 +82,48 @@ def test_autotune_and_tune_cache(tmp_path):
             for k in out:
                 assert np.array_equal(out[k], out2[k], equal_nan=True)
         text = open(path).read().split()
-        assert text[0] == "hrms-tune-v1" and text[1].startswith("gfx950")
+        assert text[0] == "hrms-tune-v2" and text[1].startswith("gfx950")
     finally:
         H.hrms_destroy(h)
     # a corrupt cache is ignored
     with open(path, "w") as f:
-        f.write("hrms-tune-v1 gfx950 256\n1 0 32 garbage\n")
+        f.write("hrms-tune-v2 gfx950 256\n1 0 32 garbage\n")
     h = make_handle(tune=path)
     try:
         b = H.Batch1D(xd, offsets, 2, 32).run(h)
         torch.cuda.synchronize()
         check_spectrum(b, fetch(b), seen, 0, 2, 32, check_f64=False, label="corrupt-cache")
+    finally:
+        H.hrms_destroy(h)
+
+
+# every launch shape compiled into the library, forced in turn: wg:r:chunk:top
+FUND_SHAPES = ["1024:8:16384:0", "1024:16:16384:0", "512:8:8192:0", "256:8:0:0", "256:8:0:32",
+               "256:16:0:0", "512:8:0:0", "512:8:0:32"]
+EQ1_SHAPES = ["256:8:0:0", "256:4:0:0", "512:8:0:0"]
+
+
+@pytest.mark.parametrize("variant,shape", [(v, s) for v in [1, 2, 3] for s in FUND_SHAPES] +
+                         [(0, s) for s in EQ1_SHAPES])
+def test_every_launch_shape_matches_oracle(monkeypatch, variant, shape):
+    """Ragged batch (lengths from 3 to 2^18 + 3, Hmax 32 and 8) under each
+    compiled shape, with and without the top-band split: the sampled outputs
+    of every spectrum equal the oracle's bits."""
+    import torch
+    from paper_1812_02647_amd import hrms as H
+    monkeypatch.setenv("HRMS_FORCE_SHAPE", shape)
+    lengths = [(1 << 18) + 3, 3, 70001, 65536, 9999]
+    hmax = np.array([32, 8, 32, 32, 16], np.uint8)
+    x, offsets, _ = synth.batch(len(lengths), lengths, seed=37, comb_fraction=0.6)
+    xd, seen = to_device_input(x, "f32")
+    h = make_handle()
+    try:
+        case_log(f"forced shape {shape} variant={NAMES[variant]}")
+        b = H.Batch1D(xd, offsets, variant, hmax).run(h)
+        torch.cuda.synchronize()
+        out = fetch(b)
+        for s in range(len(lengths)):
+            check_spectrum(b, out, seen, s, variant, int(hmax[s]), check_f64=False,
+                           label=f"shape {shape}")
     finally:
         H.hrms_destroy(h)

@@ -6,7 +6,7 @@ import subprocess
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def test_piece_schedules_cover_every_harmonic_once_in_order(tmp_path):
+def test_chunk_walks_cover_every_harmonic_once_in_order(tmp_path):
     exe = tmp_path / "plan_check"
     subprocess.check_call(["g++", "-O2", "-std=c++17", "-o", str(exe),
                            os.path.join(ROOT, "tests", "plan_check.cpp")])
