@@ -46,6 +46,9 @@ sys.path.insert(0, ROOT)
 METRIC = "G input bins/s and % of HBM peak, 1D batch Hmax=32, FP32 vs FP16-storage"
 HBM_PEAK_GBS = 8000.0
 VARIANT_NAMES = ["eq1", "max", "freqbin", "greedy"]
+# kernels of the default launch shapes
+KERNEL_OF = {"eq1": "k_hrms1d_eq1", "max": "k_hrms1d_span", "freqbin": "k_hrms1d_gather+k_hrms1d_span",
+             "greedy": "k_hrms1d_gather"}
 
 
 def parse():
@@ -62,7 +65,30 @@ def parse():
     ap.add_argument("--cpu-baseline-spectra", type=int, default=400,
                     help="spectra in the oracle's timed sample (0 skips it)")
     ap.add_argument("--cpu-threads", type=int, default=0, help="0: min(16, cores)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="after timing, copy the input once (a dispatch of known bytes for "
+                         "scaling the FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
+
+
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1812_02647_amd", "csrc", "hrms_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def measured_traffic(kernel: str, variant: str):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    runs (FETCH_SIZE, WRITE_SIZE, each scaled by what the counter reads for a
+    copy of known size), or None if they were taken on other kernel sources."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    digest = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    for ent in rec.get("kernels", []):
+        if ent.get("source_sha256") == digest and ent.get("variant") == variant:
+            return ent["read_bytes"] + ent["write_bytes"]
+    return None
 
 
 def alg_bytes_per_launch(total_bins: int, h_floats: int, in_bytes: int) -> int:
@@ -317,6 +343,12 @@ def workload_batch(args):
             "diff_vs_fp32_storage": diff,
         }
 
+    if args.calibrate_copy:
+        y = torch.empty_like(xd)
+        y.copy_(xd)
+        torch.cuda.synchronize()
+        del y
+
     cpu = None
     if args.cpu_baseline_spectra > 0:
         threads = args.cpu_threads or min(16, os.cpu_count() or 1)
@@ -345,12 +377,12 @@ def workload_batch(args):
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": f"k_hrms1d_{'eq1' if dom == 'eq1' else 'fund'} ({dom})",
+            "kernel": f"{KERNEL_OF[dom]} ({dom})",
             "achieved": d["achieved_gbs"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": d["frac_hbm"],
-            "traffic": None,
+            "traffic": measured_traffic(KERNEL_OF[dom], dom),
         },
         "cpu_baseline": cpu,
         "per_variant": per_variant,
