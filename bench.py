@@ -97,10 +97,21 @@ def alg_bytes_per_launch(total_bins: int, h_floats: int, in_bytes: int) -> int:
     return total_bins * in_bytes + 4 * h_floats + 4 * total_bins + 1 * total_bins
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(x, offsets, hmax, variants, n_sample, threads):
     """The oracle on n_sample spectra of the batch: statistics and every
     variant of each spectrum, one spectrum per task on a thread pool (ctypes
-    releases the GIL)."""
+    releases the GIL), as the paper parallelises its CPU code over time
+    series; plus the same on one thread for a few spectra."""
     from concurrent.futures import ThreadPoolExecutor
     from oracle import oracle as O
     O.lib()
@@ -117,11 +128,17 @@ def cpu_baseline(x, offsets, hmax, variants, n_sample, threads):
     with ThreadPoolExecutor(max_workers=threads) as ex:
         bins = sum(ex.map(work, picks))
     dt = time.perf_counter() - t0
+    one = picks[:max(1, min(4, n_sample // threads))]
+    t1 = time.perf_counter()
+    bins1 = sum(work(s) for s in one)
+    dt1 = time.perf_counter() - t1
     return {"value": bins / dt / 1e9, "unit": "G input bins/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{n_sample} of the batch's spectra x {offsets[1] - offsets[0]} bins, "
                       f"statistics + {len(variants)} variants each, FP32 evaluation, "
-                      f"{dt:.1f} s wall on {threads} threads"}
+                      f"{dt:.1f} s wall on {threads} threads",
+            "one_thread": {"value": bins1 / dt1 / 1e9, "spectra": len(one)},
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
 
 
 class Runner:
@@ -199,6 +216,24 @@ class Runner:
                 "frac_hbm": round(byts / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             }
         return step_ms, stats_ms, per, wall
+
+
+def copy_ceiling(xd) -> float:
+    """Measured copy rate (GB/s, bytes read + written) of the input on this
+    GPU: the practical ceiling a streaming kernel meets."""
+    import torch
+    y = torch.empty_like(xd)
+    y.copy_(xd)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(3):
+        y.copy_(xd)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 3
+    del y
+    return 2.0 * xd.numel() * xd.element_size() / (ms * 1e-3) / 1e9
 
 
 def per_spectrum_step_ms(H, xd, offsets, hmax, variants):
@@ -301,6 +336,9 @@ def workload_batch(args):
 
     r32 = Runner(H, handle, xd, offsets, hmax, variants, H.HRMS_F32)
     ms_per_step, stats_ms, per_variant, wall = r32.measure(args.steps, args.warmup)
+    copy_gbs = copy_ceiling(xd)
+    for v in per_variant.values():
+        v["frac_copy"] = round(v["achieved_gbs"] / copy_gbs, 4)
     dom = max(per_variant, key=lambda k: per_variant[k]["ms"])
     d = per_variant[dom]
     del r32
@@ -383,6 +421,8 @@ def workload_batch(args):
             "unit": "GB/s",
             "frac": d["frac_hbm"],
             "traffic": measured_traffic(KERNEL_OF[dom], dom),
+            "copy_ceiling_gbs": round(copy_gbs, 1),
+            "frac_of_copy_ceiling": d["frac_copy"],
         },
         "cpu_baseline": cpu,
         "per_variant": per_variant,

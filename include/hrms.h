@@ -67,8 +67,21 @@ enum { HRMS_EQ1 = 0, HRMS_MAX = 1, HRMS_FREQBIN = 2, HRMS_GREEDY = 3 };
  * any arithmetic. */
 enum { HRMS_F32 = 0, HRMS_F16 = 1, HRMS_BF16 = 2 };
 
-/* Output selection bits. */
-enum { HRMS_OUT_H = 1u, HRMS_OUT_MAXSNR = 2u, HRMS_OUT_BESTH = 4u };
+/* Output selection bits. HRMS_OUT_CAND (1D only) appends, for every bin whose
+ * maximum SNR over the levels is at least cand_threshold, one hrms_candidate
+ * record -- the thresholding step that follows the harmonic sum in a search
+ * (Sec. 1) -- fused into the harmonic-sum kernels, so that a run asking only
+ * for candidates writes no per-bin output. */
+enum { HRMS_OUT_H = 1u, HRMS_OUT_MAXSNR = 2u, HRMS_OUT_BESTH = 4u, HRMS_OUT_CAND = 8u };
+
+/* A candidate bin of a 1D batch. */
+typedef struct {
+    int32_t spectrum;         /* index in the batch */
+    int32_t bin;              /* output n (the fundamental for eq. (2)-(4), the
+                                 H-th harmonic's bin for eq. (1)) */
+    float snr;                /* its maximum SNR over the levels (bit-equal to max_snr) */
+    int32_t best_h;           /* the level H attaining it (bit-equal to best_h) */
+} hrms_candidate;
 
 enum { HRMS_STATS_COMPUTE = 0, HRMS_STATS_PROVIDED = 1 };
 
@@ -109,6 +122,13 @@ typedef struct {
     float* max_snr;           /* device: offsets[n_spectra] floats; iff OUT_MAXSNR */
     uint8_t* best_h;          /* device: offsets[n_spectra] bytes (the H value);
                                  iff OUT_BESTH */
+    hrms_candidate* cand;     /* device: cand_capacity records; iff OUT_CAND. The
+                                 order of the records is unspecified. */
+    uint32_t* cand_count;     /* device: one counter, iff OUT_CAND; set to the
+                                 number of candidates found (records past
+                                 cand_capacity are dropped, the count is not) */
+    uint32_t cand_capacity;   /* records cand can hold (0 allowed: count only) */
+    float cand_threshold;     /* SNR threshold of OUT_CAND (finite) */
 } hrms_run1d_args;
 
 /* One frequency x fdot plane: row r = z + zmax holds fdot z, z = -zmax..zmax.

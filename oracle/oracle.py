@@ -211,6 +211,16 @@ def hrms_2d(x2d, zmax: int, variant: int, hmax: int, fidx=None, zidx=None, f32: 
     return h, ms, bh, consts
 
 
+def candidates(max_snr, best_h, threshold: float):
+    """The candidate list of one spectrum: every output whose maximum SNR over
+    the levels reaches ``threshold`` (the thresholding that follows the
+    harmonic sum in a search, Sec. 1), in increasing output order, as
+    (bins, snr, best_h) arrays."""
+    ms = np.asarray(max_snr)
+    sel = np.nonzero(ms >= threshold)[0]
+    return sel.astype(np.int64), ms[sel], np.asarray(best_h)[sel]
+
+
 def scale_f32(x, mu: float):
     """binary32 product x * fl32(1/mu), before narrow rounding."""
     x = _f64(x).ravel()

@@ -171,9 +171,11 @@ int validate_1d(hrms_ctx* c, const hrms_run1d_args* a, bool device_ptrs)
         return fail(c, HRMS_E_INVAL, "variant must be HRMS_EQ1..HRMS_GREEDY");
     if (a->dtype < HRMS_F32 || a->dtype > HRMS_BF16)
         return fail(c, HRMS_E_INVAL, "dtype must be HRMS_F32, HRMS_F16 or HRMS_BF16");
-    if (a->out_mask & ~7u) return fail(c, HRMS_E_INVAL, "out_mask has unknown bits");
+    if (a->out_mask & ~15u) return fail(c, HRMS_E_INVAL, "out_mask has unknown bits");
     if (a->stats_mode != HRMS_STATS_COMPUTE && a->stats_mode != HRMS_STATS_PROVIDED)
         return fail(c, HRMS_E_INVAL, "stats_mode must be COMPUTE or PROVIDED");
+    if ((a->out_mask & HRMS_OUT_CAND) && !std::isfinite(a->cand_threshold))
+        return fail(c, HRMS_E_INVAL, "cand_threshold must be finite");
     if (!a->offsets) return fail(c, HRMS_E_INVAL, "offsets is NULL");
     if (a->offsets[0] != 0) return fail(c, HRMS_E_INVAL, "offsets[0] must be 0");
     for (int s = 0; s < a->n_spectra; ++s) {
@@ -199,6 +201,10 @@ int validate_1d(hrms_ctx* c, const hrms_run1d_args* a, bool device_ptrs)
             return fail(c, HRMS_E_INVAL, "max_snr is NULL but HRMS_OUT_MAXSNR is set");
         if ((a->out_mask & HRMS_OUT_BESTH) && !a->best_h)
             return fail(c, HRMS_E_INVAL, "best_h is NULL but HRMS_OUT_BESTH is set");
+        if ((a->out_mask & HRMS_OUT_CAND) && !a->cand_count)
+            return fail(c, HRMS_E_INVAL, "cand_count is NULL but HRMS_OUT_CAND is set");
+        if ((a->out_mask & HRMS_OUT_CAND) && a->cand_capacity > 0 && !a->cand)
+            return fail(c, HRMS_E_INVAL, "cand is NULL but cand_capacity > 0");
     }
     return HRMS_OK;
 }
@@ -741,6 +747,7 @@ hipError_t enqueue_1d(const hrms_run1d_args* a, Plan1D* P, const Shape1D& shape,
     cp.consts = (LevelConst*)P->d_consts.p;
     cp.user_consts = a->snr_consts;
     cp.counters = (unsigned int*)P->d_counter.p;
+    cp.cand_count = (a->out_mask & HRMS_OUT_CAND) ? a->cand_count : nullptr;
     cp.n_spec = a->n_spectra;
     cp.variant = a->variant;
     cp.compute_stats = compute ? 1 : 0;
@@ -758,6 +765,10 @@ hipError_t enqueue_1d(const hrms_run1d_args* a, Plan1D* P, const Shape1D& shape,
         rp.counters = (unsigned int*)P->d_counter.p;
         rp.nqueues = P->nqueues;
         rp.out_mask = a->out_mask;
+        rp.cand = reinterpret_cast<CandRec*>(a->cand);
+        rp.cand_count = a->cand_count;
+        rp.cand_cap = a->cand_capacity;
+        rp.cand_thr = a->cand_threshold;
         if (!P->tiles.empty() &&
             (e = launch_hrms1d(a->variant, a->dtype, shape, rp, P->grid, stream)) != hipSuccess)
             return e;
@@ -786,9 +797,13 @@ int run_1d_with(hrms_ctx* h, const hrms_run1d_args* a, hipStream_t stream, const
         if ((e = enqueue_1d(a, P, shape, stream)) != hipSuccess) return hip_fail(h, e, "launch");
         return HRMS_OK;
     }
+    uint32_t thr_bits;
+    std::memcpy(&thr_bits, &a->cand_threshold, sizeof thr_bits);
     const std::vector<const void*> key = {a->x, a->stats, a->snr_consts, a->h, a->max_snr,
                                           a->best_h, (const void*)(intptr_t)a->stats_mode,
-                                          (const void*)(intptr_t)a->out_mask};
+                                          (const void*)(intptr_t)a->out_mask, a->cand,
+                                          a->cand_count, (const void*)(intptr_t)a->cand_capacity,
+                                          (const void*)(intptr_t)thr_bits};
     if (!P->gexec || P->gkey != key) {
         if (!h->capture &&
             (e = hipStreamCreateWithFlags(&h->capture, hipStreamNonBlocking)) != hipSuccess)

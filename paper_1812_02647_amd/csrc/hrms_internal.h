@@ -37,6 +37,10 @@ struct Run1DParams {
     unsigned int* counters;     // [kMaxQueues] tiles claimed from each queue
     int32_t nqueues;
     uint32_t out_mask;
+    CandRec* cand;              // candidate list (out_mask bit 8)
+    unsigned int* cand_count;
+    uint32_t cand_cap;
+    float cand_thr;
 };
 
 struct StatsParams {
@@ -55,7 +59,8 @@ struct ConstsParams {
     double* stats;              // [n_spec][2]
     LevelConst* consts;         // [n_spec][kMaxLevels]
     float* user_consts;         // optional [n_spec][kMaxLevels][2]
-    unsigned int* counters;     // [kMaxQueues] reset to 0 for the following launch, or NULL
+    unsigned int* counters;     // [kCounterSlots] reset to 0 for the following launch, or NULL
+    unsigned int* cand_count;   // reset to 0, or NULL
     int32_t n_spec;
     int32_t variant;
     int32_t compute_stats;      // 1: reduce partials into stats; 0: read stats

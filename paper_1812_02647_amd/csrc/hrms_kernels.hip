@@ -169,6 +169,59 @@ __device__ __forceinline__ int claim_tile(const Run1DParams& p, int& q, int& vis
     return -1;
 }
 
+// Candidate records are gathered per workgroup in LDS and written out in one
+// block after a barrier, so that the global counter sees one atomic per
+// workgroup flush instead of one per wavefront.
+constexpr int kCandLds = 512;
+
+struct CandStage {
+    CandRec rec[kCandLds];
+    unsigned int n;      // records appended since the last flush (may pass kCandLds)
+    unsigned int base;   // global place of the flushed block
+};
+
+// Appends a record for every active lane with `take` set: one LDS atomic per
+// wavefront claims the places, the lanes write in lane order; a record that
+// finds the LDS block full goes straight to the global list.
+__device__ __forceinline__ void append_candidates(const Run1DParams& p, CandStage& cs, bool take,
+                                                  int spec, int n, float snr, int hval)
+{
+    const uint64_t m = __ballot(take);
+    if (m == 0) return;
+    const int lane = (int)(threadIdx.x & 63);
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    unsigned int base = 0;
+    if (lane == leader) base = atomicAdd(&cs.n, (unsigned int)__popcll(m));
+    base = (unsigned int)__shfl((int)base, leader, 64);
+    if (take) {
+        const unsigned int k = base + (unsigned int)__popcll(m & ((1ull << lane) - 1ull));
+        const CandRec rec{spec, n, snr, hval};
+        if (k < (unsigned int)kCandLds) {
+            cs.rec[k] = rec;
+        } else {
+            const unsigned int g = atomicAdd(p.cand_count, 1u);
+            if (g < p.cand_cap) p.cand[g] = rec;
+        }
+    }
+}
+
+// Writes the workgroup's staged records to the global list. Called by every
+// thread right after a barrier that follows all appends; no append may start
+// before the barrier that ends this call.
+__device__ __forceinline__ void flush_candidates(const Run1DParams& p, CandStage& cs, int wg)
+{
+    const unsigned int nc = (unsigned int)uniform((int)cs.n);
+    if (nc == 0) return;
+    const unsigned int m = nc < (unsigned int)kCandLds ? nc : (unsigned int)kCandLds;
+    if (threadIdx.x == 0) cs.base = atomicAdd(p.cand_count, m);
+    __syncthreads();   // base visible; every thread has read cs.n
+    if (threadIdx.x == 0) cs.n = 0u;
+    const unsigned int base = cs.base;
+    for (unsigned int k = threadIdx.x; k < m; k += (unsigned int)wg)
+        if (base + k < p.cand_cap) p.cand[base + k] = cs.rec[k];
+    __syncthreads();   // the block is read out before the next appends
+}
+
 // --------------------------------------------------------------------------
 // eq. (2)-(4): outputs indexed by the fundamental.
 //
@@ -255,8 +308,27 @@ __device__ __forceinline__ float term_value(const float* buf, int k, int idx, in
     if constexpr (VAR == kFreqbin) {
         return buf[idx];
     } else if constexpr (VAR == kMax) {
+        // the window's bins are read in blocks issued together; the running
+        // maximum scans them in order (with a strict >, only the first bin's
+        // value decides a NaN result, so the grouping changes no bit)
         float tv = buf[idx];
-        for (int jj = 1; jj < i; ++jj) {
+        int jj = 1;
+        for (; jj + 8 <= i; jj += 8) {
+            float w[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) w[u] = buf[pidx(k + jj + u)];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) tv = w[u] > tv ? w[u] : tv;
+        }
+        if (jj + 4 <= i) {
+            float w[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) w[u] = buf[pidx(k + jj + u)];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) tv = w[u] > tv ? w[u] : tv;
+            jj += 4;
+        }
+        for (; jj < i; ++jj) {
             const float w = buf[pidx(k + jj)];
             tv = w > tv ? w : tv;
         }
@@ -280,7 +352,7 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t out_rsrc(const void* base, int
                                              kBufferFlags);
 }
 
-template <int VAR, int DT, int WG, int R, int CB>
+template <int VAR, int DT, int WG, int R, int CB, bool CAND>
 __global__ __launch_bounds__(WG) void k_hrms1d_span(const Run1DParams p)
 {
     constexpr int V = Elem<DT>::kVec;
@@ -294,11 +366,13 @@ __global__ __launch_bounds__(WG) void k_hrms1d_span(const Run1DParams p)
     constexpr int TSH = __builtin_ctz(WG);
     __shared__ float lds[2][LDSB];
     __shared__ int ring[2];
+    __shared__ CandStage cands;
 
     const int tid = (int)threadIdx.x;
     const int lane = tid & 63;
     const int wbase = uniform(tid & ~63);   // first thread of this wave
-    const bool track = (p.out_mask & 6u) != 0;
+    if (tid == 0) cands.n = 0u;
+    const bool track = CAND || (p.out_mask & 6u) != 0;
     int cq = (int)(blockIdx.x % (unsigned)p.nqueues), visited = 0;
     if (tid == 0) {
         ring[0] = claim_tile(p, cq, visited);
@@ -461,12 +535,16 @@ __global__ __launch_bounds__(WG) void k_hrms1d_span(const Run1DParams p)
                             if (p.out_mask & 4u)
                                 __builtin_amdgcn_raw_buffer_store_b8(
                                     (uint8_t)(1u << (st[r] & 255)), brs, tid, r * WG, 0);
+                            if constexpr (CAND)
+                                append_candidates(p, cands, best[r] >= p.cand_thr, d0.t.spec,
+                                                  a + r * WG + tid, best[r], 1 << (st[r] & 255));
                         }
                     }
                 }
             }
         }
         __syncthreads();   // chunk k done; chunk k + 1 visible
+        if constexpr (CAND) flush_candidates(p, cands, WG);
         d0 = d1;
         h0 = h1;
         d1 = d2;
@@ -500,13 +578,17 @@ __device__ __forceinline__ float buffer_elem(__amdgpu_buffer_rsrc_t rs, int pos)
 }
 
 
-template <int DT, int WG, int R, int CB>
+template <int DT, int WG, int R, int CB, bool CAND>
 __global__ __launch_bounds__(WG) void k_hrms1d_eq1(const Run1DParams p)
 {
     const int tid = (int)threadIdx.x;
     __shared__ int s_claim[2];
+    __shared__ CandStage cands;
     int cq = (int)(blockIdx.x % (unsigned)p.nqueues), visited = 0;
-    if (tid == 0) s_claim[0] = claim_tile(p, cq, visited);
+    if (tid == 0) {
+        s_claim[0] = claim_tile(p, cq, visited);
+        cands.n = 0u;
+    }
     __syncthreads();
     int t = uniform(s_claim[0]);
     for (int c = 0; t >= 0; ++c) {
@@ -584,8 +666,12 @@ __global__ __launch_bounds__(WG) void k_hrms1d_eq1(const Run1DParams p)
                 if (p.out_mask & 2u) p.max_snr[ct.xoff + nn[r]] = best[r];
                 if (p.out_mask & 4u) p.best_h[ct.xoff + nn[r]] = (uint8_t)(1u << bl[r]);
             }
+            if constexpr (CAND)
+                append_candidates(p, cands, act[r] && best[r] >= p.cand_thr, ct.spec, nn[r],
+                                  best[r], 1 << bl[r]);
         }
         __syncthreads();
+        if constexpr (CAND) flush_candidates(p, cands, WG);
         t = uniform(s_claim[(c + 1) & 1]);
     }
 }
@@ -601,15 +687,19 @@ __global__ __launch_bounds__(WG) void k_hrms1d_eq1(const Run1DParams p)
 // memory-side cache serve the reuse). Each output adds its terms in the
 // order i = 1..H; snapshots as in the LDS form.
 // --------------------------------------------------------------------------
-template <int VAR, int DT, int WG, int R>
+template <int VAR, int DT, int WG, int R, bool CAND>
 __global__ __launch_bounds__(WG) void k_hrms1d_gather(const Run1DParams p)
 {
     const int tid = (int)threadIdx.x;
     const int lane = tid & 63;
-    const bool track = (p.out_mask & 6u) != 0;
+    const bool track = CAND || (p.out_mask & 6u) != 0;
     __shared__ int s_claim[2];
+    __shared__ CandStage cands;
     int cq = (int)(blockIdx.x % (unsigned)p.nqueues), visited = 0;
-    if (tid == 0) s_claim[0] = claim_tile(p, cq, visited);
+    if (tid == 0) {
+        s_claim[0] = claim_tile(p, cq, visited);
+        cands.n = 0u;
+    }
     __syncthreads();
     int t = uniform(s_claim[0]);
     int cur_spec = -1;
@@ -725,10 +815,14 @@ __global__ __launch_bounds__(WG) void k_hrms1d_gather(const Run1DParams p)
                                     (uint8_t)(1u << (st[r] & 255)), brs, tid, r * WG, 0);
                         }
                     }
+                    if (CAND && fin)
+                        append_candidates(p, cands, act[r] && best[r] >= p.cand_thr, ct.spec,
+                                          nn[r], best[r], 1 << (st[r] & 255));
                 }
             }
         }
         __syncthreads();
+        if constexpr (CAND) flush_candidates(p, cands, WG);
         t = uniform(s_claim[(c + 1) & 1]);
     }
 }
@@ -827,6 +921,7 @@ __global__ __launch_bounds__(64) void k_consts(const ConstsParams p)
     const int s = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (s == 0 && p.counters)
         for (int q = 0; q < kCounterSlots; ++q) p.counters[q] = 0u;
+    if (s == 0 && p.cand_count) *p.cand_count = 0u;
     if (s >= p.n_spec) return;
     const SpecDesc sd = p.spec[s];
     double mu, sigma;
@@ -1005,19 +1100,19 @@ __global__ __launch_bounds__(kStatsWG) void k_quantize(const QuantParams p)
     }
 }
 
-template <int VAR, int DT, int WG, int R, int C>
+template <int VAR, int DT, int WG, int R, int C, bool CAND>
 void* fund_kernel()
 {
     if constexpr (C == 0)
-        return reinterpret_cast<void*>(&k_hrms1d_gather<VAR, DT, WG, R>);
+        return reinterpret_cast<void*>(&k_hrms1d_gather<VAR, DT, WG, R, CAND>);
     else
-        return reinterpret_cast<void*>(&k_hrms1d_span<VAR, DT, WG, R, C>);
+        return reinterpret_cast<void*>(&k_hrms1d_span<VAR, DT, WG, R, C, CAND>);
 }
 
-template <int DT, int WG, int R, int C>
+template <int DT, int WG, int R, int C, bool CAND>
 void* eq1_kernel()
 {
-    return reinterpret_cast<void*>(&k_hrms1d_eq1<DT, WG, R, C>);
+    return reinterpret_cast<void*>(&k_hrms1d_eq1<DT, WG, R, C, CAND>);
 }
 
 // Launch shapes compiled into the library: (threads, outputs per thread, LDS
@@ -1025,31 +1120,48 @@ void* eq1_kernel()
 struct ShapeEntry {
     int eq1;   // 1: eq. (1) kernel family, 0: eq. (2)-(4)
     int wg, r, chunk;
-    void* (*k[3][3])();   // [variant slot][dtype]
+    void* (*k[3][3][2])();   // [variant slot][dtype][with candidate output]
 };
+
+template <int VAR, int WG, int R, int CB>
+constexpr auto fund_dtypes()
+{
+    struct T {
+        void* (*k[3][2])();
+    };
+    return T{{{&fund_kernel<VAR, kF32, WG, R, CB, false>, &fund_kernel<VAR, kF32, WG, R, CB, true>},
+              {&fund_kernel<VAR, kF16, WG, R, CB, false>, &fund_kernel<VAR, kF16, WG, R, CB, true>},
+              {&fund_kernel<VAR, kBF16, WG, R, CB, false>,
+               &fund_kernel<VAR, kBF16, WG, R, CB, true>}}};
+}
 
 template <int WG, int R, int CB>
 constexpr ShapeEntry fund_shape()
 {
-    return ShapeEntry{0, WG, R, CB,
-                      {{&fund_kernel<kMax, kF32, WG, R, CB>, &fund_kernel<kMax, kF16, WG, R, CB>,
-                        &fund_kernel<kMax, kBF16, WG, R, CB>},
-                       {&fund_kernel<kFreqbin, kF32, WG, R, CB>,
-                        &fund_kernel<kFreqbin, kF16, WG, R, CB>,
-                        &fund_kernel<kFreqbin, kBF16, WG, R, CB>},
-                       {&fund_kernel<kGreedy, kF32, WG, R, CB>,
-                        &fund_kernel<kGreedy, kF16, WG, R, CB>,
-                        &fund_kernel<kGreedy, kBF16, WG, R, CB>}}};
+    ShapeEntry e{0, WG, R, CB, {}};
+    const auto mx = fund_dtypes<kMax, WG, R, CB>();
+    const auto fb = fund_dtypes<kFreqbin, WG, R, CB>();
+    const auto gr = fund_dtypes<kGreedy, WG, R, CB>();
+    for (int d = 0; d < 3; ++d)
+        for (int c = 0; c < 2; ++c) {
+            e.k[0][d][c] = mx.k[d][c];
+            e.k[1][d][c] = fb.k[d][c];
+            e.k[2][d][c] = gr.k[d][c];
+        }
+    return e;
 }
 
 template <int WG, int R, int CB>
 constexpr ShapeEntry eq1_shape()
 {
-    return ShapeEntry{1, WG, R, CB,
-                      {{&eq1_kernel<kF32, WG, R, CB>, &eq1_kernel<kF16, WG, R, CB>,
-                        &eq1_kernel<kBF16, WG, R, CB>},
-                       {nullptr, nullptr, nullptr},
-                       {nullptr, nullptr, nullptr}}};
+    ShapeEntry e{1, WG, R, CB, {}};
+    e.k[0][0][0] = &eq1_kernel<kF32, WG, R, CB, false>;
+    e.k[0][0][1] = &eq1_kernel<kF32, WG, R, CB, true>;
+    e.k[0][1][0] = &eq1_kernel<kF16, WG, R, CB, false>;
+    e.k[0][1][1] = &eq1_kernel<kF16, WG, R, CB, true>;
+    e.k[0][2][0] = &eq1_kernel<kBF16, WG, R, CB, false>;
+    e.k[0][2][1] = &eq1_kernel<kBF16, WG, R, CB, true>;
+    return e;
 }
 
 const ShapeEntry kShapes[] = {
@@ -1072,12 +1184,12 @@ const ShapeEntry* find_shape(int variant, const Shape1D& s)
     return nullptr;
 }
 
-void* kernel_for(int variant, int dtype, const Shape1D& s)
+void* kernel_for(int variant, int dtype, const Shape1D& s, bool cand = false)
 {
     if (dtype < 0 || dtype > 2 || variant < 0 || variant > 3) return nullptr;
     const ShapeEntry* e = find_shape(variant, s);
     if (!e) return nullptr;
-    return variant == kEq1 ? e->k[0][dtype]() : e->k[variant - 1][dtype]();
+    return variant == kEq1 ? e->k[0][dtype][cand]() : e->k[variant - 1][dtype][cand]();
 }
 
 }  // namespace
@@ -1156,7 +1268,7 @@ int hrms1d_max_blocks_per_cu(int variant, int dtype, const Shape1D& shape, hipEr
 hipError_t launch_hrms1d(int variant, int dtype, const Shape1D& shape, const Run1DParams& p,
                          int grid, hipStream_t s)
 {
-    void* k = kernel_for(variant, dtype, shape);
+    void* k = kernel_for(variant, dtype, shape, (p.out_mask & 8u) != 0);
     if (!k) return hipErrorInvalidValue;
     if (grid <= 0) return hipSuccess;
     Run1DParams pc = p;

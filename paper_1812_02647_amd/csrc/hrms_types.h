@@ -31,6 +31,14 @@ struct TileRec {
     int32_t pad;
 };
 
+// A candidate bin (same layout as hrms_candidate in hrms.h).
+struct CandRec {
+    int32_t spec;
+    int32_t n;
+    float snr;
+    int32_t h;
+};
+
 // A segment of one spectrum for the statistics reduction.
 struct Seg {
     int32_t spec;

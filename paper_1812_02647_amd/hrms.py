@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libhrms.so")
 
 HRMS_EQ1, HRMS_MAX, HRMS_FREQBIN, HRMS_GREEDY = 0, 1, 2, 3
 HRMS_F32, HRMS_F16, HRMS_BF16 = 0, 1, 2
-HRMS_OUT_H, HRMS_OUT_MAXSNR, HRMS_OUT_BESTH = 1, 2, 4
+HRMS_OUT_H, HRMS_OUT_MAXSNR, HRMS_OUT_BESTH, HRMS_OUT_CAND = 1, 2, 4, 8
 HRMS_OUT_ALL = 7
 HRMS_STATS_COMPUTE, HRMS_STATS_PROVIDED = 0, 1
 HRMS_OK, HRMS_E_INVAL, HRMS_E_UNSUPPORTED, HRMS_E_NODEVICE, HRMS_E_NOMEM, HRMS_E_HIP = (
@@ -52,7 +52,16 @@ class hrms_run1d_args(C.Structure):
         ("h", C.c_void_p),
         ("max_snr", C.c_void_p),
         ("best_h", C.c_void_p),
+        ("cand", C.c_void_p),
+        ("cand_count", C.c_void_p),
+        ("cand_capacity", C.c_uint32),
+        ("cand_threshold", C.c_float),
     ]
+
+
+class hrms_candidate(C.Structure):
+    _fields_ = [("spectrum", C.c_int32), ("bin", C.c_int32), ("snr", C.c_float),
+                ("best_h", C.c_int32)]
 
 
 class hrms_run2d_args(C.Structure):
@@ -233,7 +242,7 @@ class Batch1D:
     host (numpy); ``x`` and every output are torch tensors on the device."""
 
     def __init__(self, x, offsets, variant, hmax, out_mask=HRMS_OUT_ALL, stats=None,
-                 want_consts=True):
+                 want_consts=True, cand_capacity=0, cand_threshold=6.0):
         import torch
         self.x = x
         self.offsets = np.ascontiguousarray(offsets, np.int64)
@@ -268,6 +277,15 @@ class Batch1D:
             if out_mask & HRMS_OUT_MAXSNR else None
         self.best_h = torch.empty(total, dtype=torch.uint8, device=dev) \
             if out_mask & HRMS_OUT_BESTH else None
+        # candidate list: records of 4 int32 words (spectrum, bin, snr bits, best H)
+        self.cand = torch.zeros((max(cand_capacity, 1), 4), dtype=torch.int32, device=dev) \
+            if out_mask & HRMS_OUT_CAND else None
+        self.cand_count = torch.zeros(1, dtype=torch.int32, device=dev) \
+            if out_mask & HRMS_OUT_CAND else None
+        a.cand = self.cand.data_ptr() if self.cand is not None else None
+        a.cand_count = self.cand_count.data_ptr() if self.cand_count is not None else None
+        a.cand_capacity = cand_capacity if out_mask & HRMS_OUT_CAND else 0
+        a.cand_threshold = cand_threshold
         a.stats = self.stats.data_ptr()
         a.snr_consts = self.consts.data_ptr() if self.consts is not None else None
         a.h = self.h.data_ptr() if self.h is not None else None
@@ -277,6 +295,17 @@ class Batch1D:
     def run(self, handle, stream=None):
         hrms_run_1d(handle, self.args, stream)
         return self
+
+    def candidates(self):
+        """(count, records): records as a numpy structured array of the first
+        min(count, capacity) candidates, in the order the kernels wrote them."""
+        n = int(self.cand_count.cpu()[0])
+        raw = self.cand[:min(n, self.args.cand_capacity)].cpu().numpy()
+        rec = np.empty(raw.shape[0], dtype=[("spectrum", np.int32), ("bin", np.int32),
+                                             ("snr", np.float32), ("best_h", np.int32)])
+        rec["spectrum"], rec["bin"], rec["best_h"] = raw[:, 0], raw[:, 1], raw[:, 3]
+        rec["snr"] = raw[:, 2].view(np.float32)
+        return n, rec
 
     def level(self, s: int, l: int):
         """Level l (H = 2^l) plane of spectrum s, as a view of ``h``."""

@@ -31,7 +31,8 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layouts_match_header():
     # sizes of the argument structs as the header lays them out (LP64)
-    assert C.sizeof(H.hrms_run1d_args) == 6 * 4 + 8 * 8
+    assert C.sizeof(H.hrms_run1d_args) == 6 * 4 + 10 * 8 + 2 * 4
+    assert C.sizeof(H.hrms_candidate) == 16
     assert C.sizeof(H.hrms_run2d_args) == 8 * 4 + 8 + 6 * 8
     assert C.sizeof(H.hrms_quantize_args) == 4 * 4 + 5 * 8
 
@@ -96,7 +97,7 @@ def layout_status(a):
     (dict(offsets=[0, 10, 20], hmax=[8, 12]), "spectrum 1"),
     (dict(offsets=[0, 10], variant=4), "variant"),
     (dict(offsets=[0, 10], dtype=3), "dtype"),
-    (dict(offsets=[0, 10], out_mask=8), "out_mask"),
+    (dict(offsets=[0, 10], out_mask=16), "out_mask"),
     (dict(offsets=[0, 10], stats_mode=2), "stats_mode"),
 ])
 def test_validation_errors(bad, msg):
@@ -154,3 +155,12 @@ def test_layout_2d_and_unsupported_variants():
     a.ld = 1000
     a.reserved = 1
     assert H.lib().hrms_layout_2d(C.byref(a), None, None) == H.HRMS_E_INVAL
+
+
+def test_candidate_threshold_must_be_finite():
+    a = make_args([0, 100], out_mask=H.HRMS_OUT_CAND)
+    a.cand_threshold = float("nan")
+    st, _ = layout_status(a)
+    assert st == H.HRMS_E_INVAL and "cand_threshold" in H.last_error(None)
+    a.cand_threshold = 6.0
+    assert layout_status(a)[0] == H.HRMS_OK

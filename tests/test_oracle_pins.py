@@ -374,6 +374,29 @@ def test_null_calibration_on_exponential_noise(variant):
         assert abs(snr.std() - 1.0) < 0.03, (NAMES[variant], l, snr.std())
 
 
+def test_candidates_noise_rate_and_comb():
+    """Thresholding of the maximum SNR. At Hmax = 1 the standardised SNR of
+    exponential noise is x - 1, so SNR >= 6 has probability e^-7: the count on
+    2^20 bins must agree within five binomial sigmas (a flipped comparison, an
+    unstandardised SNR or a dropped level would not). An on-bin comb of
+    amplitude 20/i at bin 1000 must be a candidate with its level."""
+    N = 1 << 20
+    x = synth.exponential(4242, 3, N).astype(np.float64)
+    _, ms, bh, _ = O.hrms_1d(x, O.FREQBIN, 1, f32=False, mu=1.0, sigma=1.0)
+    bins, snr, hh = O.candidates(ms, bh, 6.0)
+    p = math.exp(-7.0)
+    assert abs(bins.size - N * p) < 5 * math.sqrt(N * p * (1 - p)), bins.size
+    assert np.all(snr >= 6.0) and np.all(hh == 1) and np.all(np.diff(bins) > 0)
+    xs = synth.single_spectrum(n=1 << 16, f0=1000, harmonics=8).astype(np.float64)
+    for v in (O.MAX, O.FREQBIN, O.GREEDY):
+        _, ms, bh, _ = O.hrms_1d(xs, v, 8, f32=True)
+        bins, snr, hh = O.candidates(ms, bh, 6.0)
+        k = np.searchsorted(bins, 1000)
+        assert k < bins.size and bins[k] == 1000, NAMES[v]
+        assert hh[k] == bh[1000] and snr[k] == ms[1000]
+        assert snr[k] == ms.max(), NAMES[v]
+
+
 def test_best_level_choice_and_ties():
     # zero noise except one on-bin comb: every level's SNR is known in closed
     # form; the comb's output must pick the level with the largest of them.
