@@ -28,7 +28,7 @@ The JSON line also carries:
 
 --workload uneven: 512 spectra of log-uniform length 2^14..2^23 with Hmax in
 {8, 16, 32}: one graph-captured persistent launch vs per-spectrum launches.
---workload plane: 85 fdot rows x 2^21 bins, Hmax = 16, freq-bin and Greedy.
+--workload plane: 85 fdot rows x 2^21 bins, Hmax = 16, all four variants.
 """
 from __future__ import annotations
 
@@ -344,6 +344,27 @@ def workload_batch(args):
     del r32
     torch.cuda.empty_cache()
 
+    # candidate-only form (HRMS_OUT_CAND, SNR >= 6): no per-bin output
+    cand = {}
+    sa = H.Batch1D(xd, offsets, variants[0], hmax, out_mask=0, want_consts=False).run(handle)
+    stc = sa.stats   # statistics computed once, provided to every candidate run
+    for v in variants:
+        b = H.Batch1D(xd, offsets, v, hmax, out_mask=H.HRMS_OUT_CAND, stats=stc,
+                      want_consts=False, cand_capacity=1 << 23, cand_threshold=6.0)
+        b.run(handle)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(max(1, args.steps)):
+            b.run(handle)
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) / max(1, args.steps)
+        cand[VARIANT_NAMES[v]] = {"ms": round(t, 4), "gbins_per_s": round(total / t / 1e6, 2),
+                                  "candidates": b.candidates()[0]}
+        del b
+    del sa
+
     fp16 = None
     if not args.no_fp16:
         y = torch.empty(total, dtype=torch.float16, device=dev)
@@ -427,6 +448,7 @@ def workload_batch(args):
         "cpu_baseline": cpu,
         "per_variant": per_variant,
         "stats_ms": round(stats_ms, 4),
+        "candidates_only": cand,
         "fp16_storage": fp16,
         "wall_s_timed": round(wall, 3),
         "gen_s": round(t_gen, 1),
@@ -519,7 +541,7 @@ def workload_plane(args):
     rows = 2 * zmax + 1
     handle = H.hrms_create(0)
     res = {}
-    for v in (H.HRMS_FREQBIN, H.HRMS_GREEDY):
+    for v in (H.HRMS_EQ1, H.HRMS_MAX, H.HRMS_FREQBIN, H.HRMS_GREEDY):
         a = H.hrms_run2d_args()
         a.nf, a.zmax, a.hmax, a.variant, a.ld, a.out_mask = nf, zmax, hmax, v, nf, 7
         offs, tot = H.hrms_layout_2d(a)
@@ -550,7 +572,7 @@ def workload_plane(args):
             "ms_per_step": round(tot_ms, 4), "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "2D f-fdot plane 85 x 2^21 FP32, 20 accelerated combs, "
-                                   "Hmax=16, freq-bin + Greedy (stats included)"},
+                                   "Hmax=16, eq. (1), Max, freq-bin, Greedy (stats included)"},
             "per_variant": res}
 
 

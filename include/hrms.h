@@ -13,8 +13,8 @@
  *                                  strictly larger
  *
  * over batches of 1D power spectra (the periodicity search after the FFT,
- * Sec. 1) and, for FREQBIN and GREEDY, over a 2D frequency x fdot plane (the
- * sum that follows the Fourier-domain acceleration search; abstract, Sec. 1).
+ * Sec. 1) and over a 2D frequency x fdot plane (the sum that follows the
+ * Fourier-domain acceleration search; abstract, Sec. 1).
  *
  * Conventions shared by every entry point
  *   - Levels are H = 1, 2, 4, ..., hmax with hmax a power of two <= 32
@@ -132,15 +132,19 @@ typedef struct {
 } hrms_run1d_args;
 
 /* One frequency x fdot plane: row r = z + zmax holds fdot z, z = -zmax..zmax.
- * Output (m, z) of level H is the fundamental at frequency bin m whose H-th
- * harmonic has fdot z; harmonic i is read at frequency i*m (FREQBIN) or
- * i*m + j (GREEDY, j as in eq. (4)) from row round(i z / H) + zmax. Output
- * (m, z) of level H exists for m < floor(nf / H). */
+ * The paper names this sum (abstract, Sec. 1) without defining it; it is read
+ * as the variant's 1D sum along frequency with each harmonic taken from its
+ * own fdot row. Output (m, z) of level H is the fundamental at frequency bin m
+ * whose H-th harmonic has fdot z; harmonic i is read from row
+ * round(i z / H) + zmax (halves away from zero) at frequency round(i m / H)
+ * (EQ1, halves up), the window i*m .. i*m + i - 1 (MAX), i*m (FREQBIN) or
+ * i*m + j (GREEDY, j as in eq. (4)). As in 1D, output (m, z) of level H exists
+ * for every m with EQ1 and for m < floor(nf / H) otherwise. */
 typedef struct {
     int32_t nf;               /* frequency bins per row, 1 .. HRMS_MAX_BINS */
     int32_t zmax;             /* >= 0 */
     int32_t hmax;             /* power of two <= 32 */
-    int32_t variant;          /* HRMS_FREQBIN or HRMS_GREEDY (others: HRMS_E_UNSUPPORTED) */
+    int32_t variant;          /* HRMS_EQ1 .. HRMS_GREEDY */
     int32_t dtype;
     uint32_t out_mask;
     int32_t stats_mode;
@@ -149,8 +153,9 @@ typedef struct {
     const void* x;            /* device: (2 zmax + 1) rows of ld bins, element-aligned */
     double* stats;            /* device: [2] = (mu, sigma) over the nf bins of every row */
     float* snr_consts;        /* device or NULL: [HRMS_MAX_LEVELS][2] */
-    float* h;                 /* device: level H plane [2 zmax + 1][floor(nf / H)],
-                                 packed level after level (hrms_layout_2d) */
+    float* h;                 /* device: level H plane [2 zmax + 1][nf] (EQ1) or
+                                 [2 zmax + 1][floor(nf / H)], packed level after
+                                 level (hrms_layout_2d) */
     float* max_snr;           /* device: [2 zmax + 1][nf] */
     uint8_t* best_h;          /* device: [2 zmax + 1][nf] */
 } hrms_run2d_args;
@@ -212,7 +217,7 @@ int hrms_run_1d(hrms_handle h, const hrms_run1d_args* a, void* hip_stream);
 int hrms_autotune_1d(hrms_handle h, const hrms_run1d_args* a, void* hip_stream, int reps,
                      int32_t* chosen);
 
-/* Harmonic sum of a 2D plane (FREQBIN and GREEDY). */
+/* Harmonic sum of a 2D plane, any variant. */
 int hrms_run_2d(hrms_handle h, const hrms_run2d_args* a, void* hip_stream);
 
 /* Normalise and store FP32 spectra as FP16 / BF16 (precision form of the 1D

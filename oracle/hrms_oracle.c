@@ -303,26 +303,47 @@ int oracle_hrms_1d(const double* x, int64_t N, int variant, int hmax, const int6
 /*
  * The plane holds rows r = z + zmax for z = -zmax..zmax, each of nf frequency
  * bins, row stride ld. The 2D sum is named but not defined in the paper
- * (abstract, Sec. 1). It is read as eq. (1) applied to both axes: output
- * (f, z) at level H is the H-th harmonic, and harmonic i is sampled at
- * (i*f/H, i*z/H). The freq-bin form evaluates it at f = H*m, so the frequency
- * index is exactly i*m, and the fdot row is i*z/H rounded half away from zero.
- * Output (m, z) of level H exists for m < floor(nf / H).
+ * (abstract, Sec. 1). It is read as the 1D sums applied along frequency, with
+ * harmonic i of output (f, z) at level H taken from the fdot row nearest to
+ * i*z/H: a signal whose H-th harmonic drifts by z bins has its i-th harmonic
+ * drifting by i*z/H. The row is row_i = round_half_away(i*z, H) + zmax
+ * (halves away from zero, so that z and -z map to mirror rows).
  *
+ *   EQ1    :  S_H(f, z) = sum_{i=1..H} x[row_i][round_half_up(i*f, H)]
+ *             (eq. (1) on both axes; every f in [0, nf) has every level)
+ *   MAX    :  S_H(m, z) = sum_{i=1..H} max_{j=0..i-1} x[row_i][i*m + j]
  *   FREQBIN:  S_H(m, z) = sum_{i=1..H} x[row_i][i*m]
  *   GREEDY :  eq. (4) along frequency with harmonic k read from row_k:
  *             start at x[row_1][m], j = 0; for k = 2..H take the larger of
  *             x[row_k][k*m + j] and x[row_k][k*m + j + 1] (the right one only
  *             if strictly larger, then j += 1)
- * with row_i = round_half_away(i*z, H) + zmax. Each level is computed on its
- * own, since the row sampled for harmonic i depends on H.
+ * Outputs (m, z) of eq. (2)-(4) at level H exist for m < floor(nf / H), as in
+ * 1D. Each level is computed on its own, since the row sampled for harmonic i
+ * depends on H.
  */
 static double sum_2d(const double* x, int64_t ld, int zmax, int variant, int H, int64_t mbin, int z,
                      int f32)
 {
-    double acc;
+    double acc = 0.0;
+    if (variant == OV_EQ1) {
+        for (int i = 1; i <= H; ++i) {
+            int64_t row = round_half_away((int64_t)i * z, H) + zmax;
+            acc = rnd(f32, acc + x[row * ld + round_half_up((int64_t)i * mbin, H)]);
+        }
+        return acc;
+    }
+    if (variant == OV_MAX) {
+        for (int i = 1; i <= H; ++i) {
+            int64_t row = round_half_away((int64_t)i * z, H) + zmax;
+            const double* w = x + row * ld + (int64_t)i * mbin;
+            double m = w[0];
+            for (int j = 1; j < i; ++j)
+                if (w[j] > m) m = w[j];
+            acc = rnd(f32, acc + m);
+        }
+        return acc;
+    }
     if (variant == OV_FREQBIN) {
-        acc = 0.0;
         for (int i = 1; i <= H; ++i) {
             int64_t row = round_half_away((int64_t)i * z, H) + zmax;
             acc = rnd(f32, acc + x[row * ld + (int64_t)i * mbin]);
@@ -366,7 +387,7 @@ int oracle_hrms_2d(const double* x, int64_t ld, int64_t nf, int zmax, int varian
 {
     int nl = oracle_num_levels(hmax);
     if (nl < 1 || nf < 1 || zmax < 0 || ld < nf || !x) return OE_INVAL;
-    if (variant != OV_FREQBIN && variant != OV_GREEDY) return OE_INVAL;
+    if (variant < OV_EQ1 || variant > OV_GREEDY) return OE_INVAL;
     int64_t rows = 2 * (int64_t)zmax + 1;
     if (!fidx) cnt = rows * nf;
     for (int64_t k = 0; k < cnt; ++k) {
@@ -377,7 +398,7 @@ int oracle_hrms_2d(const double* x, int64_t ld, int64_t nf, int zmax, int varian
         int best_level = 0;
         for (int l = 0; l < nl; ++l) {
             int H = 1 << l;
-            if (!(mb < nf / H)) {
+            if (!level_valid_1d(variant, mb, nf, H)) {
                 if (h) h[(int64_t)l * cnt + k] = NAN;
                 continue;
             }

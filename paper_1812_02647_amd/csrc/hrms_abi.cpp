@@ -26,6 +26,8 @@ using namespace hrms;
 
 namespace {
 
+static_assert(kMaxLevels == HRMS_MAX_LEVELS, "level count of the ABI and the kernels differ");
+
 constexpr int kStatsSeg = 1 << 16;   // bins per statistics segment
 constexpr int kPlanCache = 4;
 
@@ -91,8 +93,7 @@ struct Plan2D {
     std::vector<Seg> segs;
     std::vector<int32_t> seg_first;   // {0, nsegs}
     std::vector<SpecDesc> plane;      // one descriptor: n = rows * nf
-    std::vector<int64_t> hoff;
-    DeviceBuf d_rows, d_segs, d_seg_first, d_plane, d_hoff, d_partial, d_consts;
+    DeviceBuf d_rows, d_segs, d_seg_first, d_plane, d_partial, d_consts;
 };
 
 // Precision form of a batch: statistics segments and fl32(1 / mu) per spectrum.
@@ -228,8 +229,6 @@ int validate_2d(hrms_ctx* c, const hrms_run2d_args* a, bool device_ptrs)
     if (a->reserved != 0) return fail(c, HRMS_E_INVAL, "reserved must be 0");
     if ((2 * (int64_t)a->zmax + 1) * (int64_t)a->nf > 0x7fffffffLL)
         return fail(c, HRMS_E_INVAL, "(2 zmax + 1) * nf must be below 2^31");
-    if (a->variant == HRMS_EQ1 || a->variant == HRMS_MAX)
-        return fail(c, HRMS_E_UNSUPPORTED, "the 2D sum is implemented for FREQBIN and GREEDY");
     if (device_ptrs) {
         if (!a->x) return fail(c, HRMS_E_INVAL, "x is NULL");
         if (reinterpret_cast<uintptr_t>(a->x) % dtype_bytes(a->dtype))
@@ -278,7 +277,7 @@ int64_t layout_2d_into(const hrms_run2d_args* a, int64_t* plane_offsets)
         int64_t o = -1;
         if (l < nl) {
             o = off;
-            off += rows * ((int64_t)a->nf >> l);
+            off += rows * plane_len_1d(a->variant, a->nf, l);
         }
         if (plane_offsets) plane_offsets[l] = o;
     }
@@ -545,15 +544,12 @@ int get_plan_2d(hrms_ctx* c, const hrms_run2d_args* a, hipStream_t stream, Plan2
     pl.n = (int32_t)((int64_t)rows * a->nf);
     pl.nlev = nlev;
     P->plane = {pl};
-    P->hoff.assign(kMaxLevels, -1);
-    layout_2d_into(a, P->hoff.data());
     hipError_t e;
     if ((e = upload(P->d_rows, P->rows, stream)) != hipSuccess) return hip_fail(c, e, "upload rows");
     if ((e = upload(P->d_segs, P->segs, stream)) != hipSuccess) return hip_fail(c, e, "upload segs");
     if ((e = upload(P->d_seg_first, P->seg_first, stream)) != hipSuccess)
         return hip_fail(c, e, "upload seg_first");
     if ((e = upload(P->d_plane, P->plane, stream)) != hipSuccess) return hip_fail(c, e, "upload plane");
-    if ((e = upload(P->d_hoff, P->hoff, stream)) != hipSuccess) return hip_fail(c, e, "upload hoff");
     if ((e = P->d_partial.ensure(P->segs.size() * 2 * sizeof(double))) != hipSuccess)
         return hip_fail(c, e, "alloc partials");
     if ((e = P->d_consts.ensure(kMaxLevels * sizeof(LevelConst))) != hipSuccess)
@@ -1029,7 +1025,9 @@ int hrms_run_2d(hrms_handle h, const hrms_run2d_args* a, void* hip_stream)
         rp.h = a->h;
         rp.max_snr = a->max_snr;
         rp.best_h = a->best_h;
-        rp.hoff = (const int64_t*)P->d_hoff.p;
+        // the level planes depend on the variant (eq. (1) keeps nf outputs per
+        // row), so they are laid out per call rather than cached in the plan
+        layout_2d_into(a, rp.hoff);
         rp.nf = a->nf;
         rp.zmax = a->zmax;
         rp.nlev = P->nlev;

@@ -73,7 +73,7 @@ struct Run2DParams {
     float* h;
     float* max_snr;
     uint8_t* best_h;
-    const int64_t* hoff;        // [kMaxLevels] first float of each level plane
+    int64_t hoff[kMaxLevels];   // first float of each level plane in h (-1: absent)
     int32_t nf;
     int32_t zmax;
     int32_t nlev;

@@ -960,13 +960,15 @@ __global__ __launch_bounds__(64) void k_consts(const ConstsParams p)
 }
 
 // --------------------------------------------------------------------------
-// 2D frequency x fdot plane (freq-bin and Greedy). Output (m, z) of level H is
-// the fundamental at frequency m whose H-th harmonic has fdot z; harmonic i
-// reads row round(i z / H) (halves away from zero) at frequency i m (freq-bin)
-// or i m + j (Greedy, j as in eq. (4)). Each level is summed on its own, in
-// the order i = 1..H. A thread owns one output; a workgroup holds 64
-// consecutive frequencies of kZRows fdot rows, the rows being the fastest grid
-// dimension so that neighbouring workgroups read the same columns.
+// 2D frequency x fdot plane. Output (f, z) of level H is the fundamental at
+// frequency f whose H-th harmonic has fdot z; harmonic i reads row
+// round(i z / H) (halves away from zero), and along that row the 1D form of
+// the variant: column round(i f / H) (eq. (1), halves up), the window
+// i f .. i f + i - 1 (eq. (2)), column i f (eq. (3)) or i f + j (eq. (4), j as
+// there). Each level is summed on its own, in the order i = 1..H. A thread owns
+// one output; a workgroup holds 64 consecutive frequencies of kZRows fdot rows,
+// the rows being the fastest grid dimension so that neighbouring workgroups
+// read the same columns.
 // --------------------------------------------------------------------------
 constexpr int kZRows = 4;
 
@@ -994,11 +996,35 @@ __global__ __launch_bounds__(64 * kZRows) void k_hrms2d(const Run2DParams p)
     int bl = 0;
 #pragma unroll
     for (int l = 0; l < kMaxLevels; ++l) {
-        if (l < p.nlev && m < (p.nf >> l)) {
+        // eq. (1) reads at most column f, so every level of every f exists
+        if (l < p.nlev && (VAR == kEq1 || m < (p.nf >> l))) {
             const int H = 1 << l;
-            float acc;
-            if constexpr (VAR == kFreqbin) {
-                acc = 0.0f;
+            float acc = 0.0f;
+            if constexpr (VAR == kEq1) {
+#pragma unroll
+                for (int i = 1; i <= (1 << (kMaxLevels - 1)); ++i) {
+                    if (i <= H) {
+                        const int row = row_of(i * z, l) + p.zmax;
+                        const int64_t col = ((int64_t)(2 * i) * m + H) >> (l + 1);
+                        acc = acc + load_scalar<DT>(p.x, (int64_t)row * ld + col);
+                    }
+                }
+            } else if constexpr (VAR == kMax) {
+#pragma unroll
+                for (int i = 1; i <= (1 << (kMaxLevels - 1)); ++i) {
+                    if (i <= H) {
+                        const int row = row_of(i * z, l) + p.zmax;
+                        const int64_t base = (int64_t)row * ld + (int64_t)i * m;
+                        // running maximum in window order with a strict >, as eq. (2)
+                        float w = load_scalar<DT>(p.x, base);
+                        for (int j = 1; j < i; ++j) {
+                            const float v = load_scalar<DT>(p.x, base + j);
+                            w = v > w ? v : w;
+                        }
+                        acc = acc + w;
+                    }
+                }
+            } else if constexpr (VAR == kFreqbin) {
 #pragma unroll
                 for (int i = 1; i <= (1 << (kMaxLevels - 1)); ++i) {
                     if (i <= H) {
@@ -1028,7 +1054,8 @@ __global__ __launch_bounds__(64 * kZRows) void k_hrms2d(const Run2DParams p)
             }
             const LevelConst c = p.consts[l];
             const float hv = acc * c.rh;
-            if (p.out_mask & 1u) p.h[p.hoff[l] + (int64_t)r * (p.nf >> l) + m] = hv;
+            const int plane = VAR == kEq1 ? p.nf : (p.nf >> l);
+            if (p.out_mask & 1u) p.h[p.hoff[l] + (int64_t)r * plane + m] = hv;
             const float snr = (hv - c.m) * c.q;
             if (l == 0 || snr > best) {
                 best = snr;
@@ -1276,6 +1303,14 @@ hipError_t launch_hrms1d(int variant, int dtype, const Shape1D& shape, const Run
     return hipLaunchKernel(k, dim3(grid), dim3(shape.wg), args, 0, s);
 }
 
+using Kernel2D = void (*)(const Run2DParams);
+
+template <int VAR>
+Kernel2D kernel_2d(int dtype)
+{
+    return dtype == kF32 ? k_hrms2d<VAR, kF32> : dtype == kF16 ? k_hrms2d<VAR, kF16> : k_hrms2d<VAR, kBF16>;
+}
+
 hipError_t launch_hrms2d(int variant, int dtype, const Run2DParams& p, hipStream_t s)
 {
     const int64_t mblocks = ((int64_t)p.nf + 63) / 64;
@@ -1283,21 +1318,15 @@ hipError_t launch_hrms2d(int variant, int dtype, const Run2DParams& p, hipStream
     if (blocks <= 0) return hipSuccess;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     dim3 grid((unsigned)blocks), block(64 * kZRows);
-    if (variant == kFreqbin) {
-        switch (dtype) {
-        case kF32: hipLaunchKernelGGL((k_hrms2d<kFreqbin, kF32>), grid, block, 0, s, p); break;
-        case kF16: hipLaunchKernelGGL((k_hrms2d<kFreqbin, kF16>), grid, block, 0, s, p); break;
-        default: hipLaunchKernelGGL((k_hrms2d<kFreqbin, kBF16>), grid, block, 0, s, p); break;
-        }
-    } else if (variant == kGreedy) {
-        switch (dtype) {
-        case kF32: hipLaunchKernelGGL((k_hrms2d<kGreedy, kF32>), grid, block, 0, s, p); break;
-        case kF16: hipLaunchKernelGGL((k_hrms2d<kGreedy, kF16>), grid, block, 0, s, p); break;
-        default: hipLaunchKernelGGL((k_hrms2d<kGreedy, kBF16>), grid, block, 0, s, p); break;
-        }
-    } else {
-        return hipErrorInvalidValue;
+    Kernel2D k = nullptr;
+    switch (variant) {
+    case kEq1: k = kernel_2d<kEq1>(dtype); break;
+    case kMax: k = kernel_2d<kMax>(dtype); break;
+    case kFreqbin: k = kernel_2d<kFreqbin>(dtype); break;
+    case kGreedy: k = kernel_2d<kGreedy>(dtype); break;
+    default: return hipErrorInvalidValue;
     }
+    hipLaunchKernelGGL(k, grid, block, 0, s, p);
     return hipGetLastError();
 }
 

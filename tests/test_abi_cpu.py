@@ -137,23 +137,23 @@ def test_layout_1d(variant):
     assert total == expect
 
 
-def test_layout_2d_and_unsupported_variants():
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+def test_layout_2d_and_invalid_planes(variant):
     a = H.hrms_run2d_args()
-    a.nf, a.zmax, a.hmax, a.variant, a.ld = 1000, 3, 16, H.HRMS_FREQBIN, 1000
+    a.nf, a.zmax, a.hmax, a.variant, a.ld = 1000, 3, 16, variant, 1000
     offs, total = H.hrms_layout_2d(a)
     rows = 7
     exp = [0]
     for l in range(5):
-        exp.append(exp[-1] + rows * (1000 >> l))
+        exp.append(exp[-1] + rows * (1000 if variant == H.HRMS_EQ1 else 1000 >> l))
     assert list(offs[:5]) == exp[:5] and offs[5] == -1 and total == exp[5]
-    for v in (H.HRMS_EQ1, H.HRMS_MAX):
-        a.variant = v
-        assert H.lib().hrms_layout_2d(C.byref(a), None, None) == H.HRMS_E_UNSUPPORTED
-    a.variant = H.HRMS_GREEDY
     a.ld = 999
     assert H.lib().hrms_layout_2d(C.byref(a), None, None) == H.HRMS_E_INVAL   # ld < nf
     a.ld = 1000
     a.reserved = 1
+    assert H.lib().hrms_layout_2d(C.byref(a), None, None) == H.HRMS_E_INVAL
+    a.reserved = 0
+    a.variant = 4
     assert H.lib().hrms_layout_2d(C.byref(a), None, None) == H.HRMS_E_INVAL
 
 

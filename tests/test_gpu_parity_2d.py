@@ -1,6 +1,7 @@
-"""GPU parity of the 2D harmonic sum on a frequency x fdot plane (freq-bin and
-Greedy; the sum after the acceleration search named in the abstract and Sec. 1
-of arXiv:1812.02647) against the CPU oracle, through the C ABI.
+"""GPU parity of the 2D harmonic sum on a frequency x fdot plane (eq. (1)-(4)
+along frequency, each harmonic from its own fdot row; the sum after the
+acceleration search named in the abstract and Sec. 1 of arXiv:1812.02647)
+against the CPU oracle, through the C ABI.
 
 Bar: every output bit-identical to the oracle's FP32 evaluation; sums within
 1e-5 of the binary64 oracle; statistics within 1e-12.
@@ -74,7 +75,7 @@ def check_plane(out, seen, nf, zmax, hmax, variant, fidx=None, zidx=None, stats=
                                  want_snr=False)
     r = zidx.astype(np.int64) + zmax
     for l in range(nl):
-        ln = nf >> l
+        ln = nf if variant == O.EQ1 else nf >> l
         valid = fidx < ln
         got = out["h"][out["offs"][l] + r[valid] * ln + fidx[valid]].astype(np.float64)
         exp = h32[l][valid]
@@ -101,7 +102,7 @@ def to_dev(x2d, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
-@pytest.mark.parametrize("variant", [O.FREQBIN, O.GREEDY])
+@pytest.mark.parametrize("variant", [O.EQ1, O.MAX, O.FREQBIN, O.GREEDY])
 def test_small_plane_every_output(handle, variant, dtype):
     zmax, nf = 7, 20003
     x, _ = synth.plane(nf=nf, zmax=zmax, seed=55, n_comb=4, f0_max=nf // 20)
@@ -112,7 +113,7 @@ def test_small_plane_every_output(handle, variant, dtype):
                 label=f"2d-{dtype}")
 
 
-@pytest.mark.parametrize("variant", [O.FREQBIN, O.GREEDY])
+@pytest.mark.parametrize("variant", [O.EQ1, O.MAX, O.FREQBIN, O.GREEDY])
 def test_plane_with_row_padding_and_provided_stats(handle, variant):
     import torch
     zmax, nf, ld = 3, 5001, 5008
@@ -127,7 +128,7 @@ def test_plane_with_row_padding_and_provided_stats(handle, variant):
     check_plane(out, seen, nf, zmax, 32, variant, stats=(1.1, 0.9), label="2d-ld")
 
 
-@pytest.mark.parametrize("variant", [O.FREQBIN, O.GREEDY])
+@pytest.mark.parametrize("variant", [O.EQ1, O.MAX, O.FREQBIN, O.GREEDY])
 def test_fdot_plane_full_size_sampled(handle, variant):
     """85 fdot rows x 2^21 frequency bins, Hmax = 16, 20 accelerated combs;
     sampled outputs against the oracle, plus recovery of the on-bin combs at
@@ -153,3 +154,16 @@ def test_fdot_plane_full_size_sampled(handle, variant):
         # the on-bin comb's strongest response sits at its fundamental frequency
         col = ms[:, f0]
         assert col.max() > 8.0, (f0, z0, col.max())
+
+
+def test_variants_alternate_on_one_handle(handle):
+    # the level planes of eq. (1) hold nf outputs per row, the others nf / H:
+    # switching variants on one handle with the same plane geometry must not
+    # reuse the previous variant's layout
+    zmax, nf = 2, 3001
+    x, _ = synth.plane(nf=nf, zmax=zmax, seed=57, n_comb=2, f0_max=150)
+    xd, seen = to_dev(x, "f32")
+    for variant in (O.EQ1, O.MAX, O.EQ1, O.GREEDY, O.FREQBIN, O.EQ1):
+        case_log(f"2d alternating variants: {NAMES[variant]}")
+        out = run_2d(handle, xd, nf, zmax, 8, variant)
+        check_plane(out, seen, nf, zmax, 8, variant, label=f"alt-{NAMES[variant]}")

@@ -61,6 +61,14 @@ MUTATIONS = [
      "                acc = rnd(f32, acc + b);"),
     ("2d freqbin uses the level-1 row", "int64_t row = round_half_away((int64_t)i * z, H) + zmax;\n            acc = rnd(f32, acc + x[row * ld + (int64_t)i * mbin]);",
      "int64_t row = round_half_away((int64_t)z, 1) + zmax;\n            acc = rnd(f32, acc + x[row * ld + (int64_t)i * mbin]);"),
+    ("2d rows truncate toward zero", "return a >= 0 ? round_half_up(a, b) : -round_half_up(-a, b);",
+     "return a / b;"),
+    ("2d eq1 frequency rounds down", "acc = rnd(f32, acc + x[row * ld + round_half_up((int64_t)i * mbin, H)]);",
+     "acc = rnd(f32, acc + x[row * ld + (int64_t)i * mbin / H]);"),
+    ("2d max window drops its last bin", "for (int j = 1; j < i; ++j)\n                if (w[j] > m)",
+     "for (int j = 1; j < i - 1; ++j)\n                if (w[j] > m)"),
+    ("2d max reads the fundamental's row", "            const double* w = x + row * ld + (int64_t)i * mbin;",
+     "            const double* w = x + (round_half_away((int64_t)z, H) + zmax) * ld + (int64_t)i * mbin;"),
     ("scale uses binary64 1/mu", "double inv = (double)(float)(1.0 / mu);", "double inv = 1.0 / mu;"),
 ]
 

@@ -419,7 +419,7 @@ def test_best_level_choice_and_ties():
 # 2D plane.
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("variant", [O.FREQBIN, O.GREEDY])
+@pytest.mark.parametrize("variant", [O.EQ1, O.MAX, O.FREQBIN, O.GREEDY])
 def test_2d_identity_mirror_and_reduction(variant):
     zmax, nf = 6, 700
     rng = np.random.default_rng(4)
@@ -435,15 +435,17 @@ def test_2d_identity_mirror_and_reduction(variant):
     hm, _, _, _ = O.hrms_2d(x[::-1].copy(), zmax, variant, 16, want_snr=False)
     hm = hm.reshape(h.shape)
     assert np.array_equal(hm[:, ::-1, :], h, equal_nan=True)
-    # domain
+    # domain: eq. (1) never reads past f, the others read up to H m + H - 1
     for l, H in enumerate(O.levels(16)):
-        assert np.all(np.isnan(h[l][:, nf // H:])) and not np.any(np.isnan(h[l][:, :nf // H]))
+        lim = nf if variant == O.EQ1 else nf // H
+        assert np.all(np.isnan(h[l][:, lim:])) and not np.any(np.isnan(h[l][:, :lim]))
 
 
-@pytest.mark.parametrize("variant", [O.FREQBIN, O.GREEDY])
+@pytest.mark.parametrize("variant", [O.EQ1, O.MAX, O.FREQBIN, O.GREEDY])
 def test_2d_recovers_accelerated_comb(variant):
     # harmonic i of a signal at (f0, z0) sits at (i f0, i z0); at level H the
-    # output (m = f0, z = H z0) samples rows round(i H z0 / H) = i z0 exactly.
+    # output at fdot H z0 samples rows round(i H z0 / H) = i z0 exactly, and
+    # frequency H f0 (eq. (1)) or f0 (eq. (2)-(4)) reaches column i f0.
     zmax, nf = 42, 1 << 14
     x = np.zeros((2 * zmax + 1, nf))
     f0, z0 = 300, -3
@@ -452,13 +454,36 @@ def test_2d_recovers_accelerated_comb(variant):
         x[i * z0 + zmax, i * f0] += a
     for H in [1, 2, 4, 8]:
         if abs(H * z0) <= zmax:
-            assert O.sum_2d(x, zmax, variant, H, f0, H * z0) == pytest.approx(sum(amps[:H]))
+            f = H * f0 if variant == O.EQ1 else f0
+            assert O.sum_2d(x, zmax, variant, H, f, H * z0) == pytest.approx(sum(amps[:H]))
     # constant plane
     c = np.full((2 * zmax + 1, 256), 1.5)
     h, _, _, _ = O.hrms_2d(c, zmax, variant, 16, want_snr=False)
     for l, H in enumerate(O.levels(16)):
         v = ~np.isnan(h[l])
         np.testing.assert_allclose(h[l][v], math.sqrt(H) * 1.5, rtol=1e-15)
+
+
+@pytest.mark.parametrize("variant", [O.EQ1, O.MAX, O.FREQBIN, O.GREEDY])
+def test_2d_harmonic_reads_the_nearest_row(variant):
+    # one unit impulse at column i0 m of row r: only harmonic i0 can reach it,
+    # so the level-H output at (m, z) -- frequency H m for eq. (1) -- is 1
+    # exactly when the row sampled for harmonic i0 is r. That row must be the
+    # integer nearest to i0 z / H, halves resolved away from zero.
+    zmax, H, m = 9, 8, 37
+    nf = H * m + H + 1
+    for i0 in (1, 3, 5, 8):
+        for r in range(2 * zmax + 1):
+            x = np.zeros((2 * zmax + 1, nf))
+            x[r, i0 * m] = 1.0
+            f = H * m if variant == O.EQ1 else m
+            hit = [z for z in range(-zmax, zmax + 1) if O.sum_2d(x, zmax, variant, H, f, z) != 0.0]
+            want = []
+            for z in range(-zmax, zmax + 1):
+                t, d = i0 * z / H, (r - zmax) - i0 * z / H
+                if abs(d) < 0.5 or (abs(d) == 0.5 and abs(r - zmax) > abs(t)):
+                    want.append(z)
+            assert hit == want, (i0, r, hit, want)
 
 
 def test_scale_f32():
