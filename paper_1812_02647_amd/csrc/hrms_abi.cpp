@@ -292,7 +292,7 @@ Shape1D default_shape(int variant)
 {
     // measured on the 1000 x 2^21, Hmax = 32 batch
     if (variant == HRMS_EQ1) return Shape1D{512, 8, 0, 0};
-    if (variant == HRMS_MAX) return Shape1D{1024, 8, 16384, 0};
+    if (variant == HRMS_MAX) return Shape1D{512, 8, 8192, 0};
     if (variant == HRMS_GREEDY) return Shape1D{512, 8, 0, 0};
     return Shape1D{512, 8, 0, 32};
 }

@@ -126,29 +126,39 @@ struct Stage {
             }
         }
     }
+    // Each pad word receives a copy of the bin that follows it, so that the
+    // word after any bin's word holds the next bin.
     __device__ __forceinline__ void store(float* buf, int nvec) const
     {
         constexpr int V = Elem<DT>::kVec;
         constexpr int STEP = WG * V;   // chunk positions per vector slot u
         static_assert(STEP % 32 == 0, "a vector slot spans whole padding blocks");
         // pidx(k0 + u STEP + e) = pidx(k0) + u (STEP + STEP / 32) + e for e < V
-        float* b = buf + pidx((int)threadIdx.x * V);
+        const int tid = (int)threadIdx.x;
+        float* b = buf + pidx(tid * V);
+        // a vector starting a 32-bin block (other than the chunk's first) also
+        // fills the pad word just before it
+        const bool lead = ((tid * V) & 31) == 0;
 #pragma unroll
         for (int u = 0; u < VPT; ++u) {
-            const int vi = u * WG + (int)threadIdx.x;
+            const int vi = u * WG + tid;
             if (vi < nvec) {
                 float* d = b + u * (STEP + STEP / 32);
                 const uint32_t w[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+                float f[V];
                 if constexpr (DT == kF32) {
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) d[e] = __uint_as_float(w[e]);
+                    for (int e = 0; e < 4; ++e) f[e] = __uint_as_float(w[e]);
                 } else {
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
-                        d[2 * e] = DT == kF16 ? h2f(w[e] & 0xffffu) : bf2f(w[e] & 0xffffu);
-                        d[2 * e + 1] = DT == kF16 ? h2f(w[e] >> 16) : bf2f(w[e] >> 16);
+                        f[2 * e] = DT == kF16 ? h2f(w[e] & 0xffffu) : bf2f(w[e] & 0xffffu);
+                        f[2 * e + 1] = DT == kF16 ? h2f(w[e] >> 16) : bf2f(w[e] >> 16);
                     }
                 }
+#pragma unroll
+                for (int e = 0; e < V; ++e) d[e] = f[e];
+                if (lead && vi > 0) d[-1] = f[0];
             }
         }
     }
@@ -298,46 +308,87 @@ struct ChunkCursor {
 };
 
 // Term i of an output whose window starts at chunk position k (LDS index
-// idx = pidx(k)). Greedy reads its offset j from st (bits 8..) and sets
-// step when the right neighbour is taken (j then grows by one).
+// idx = pidx(k)). The word after a bin's LDS word always holds the next bin
+// (pad words carry a copy of the bin after them), so a window of i <= 32 bins
+// is words idx .. idx + i - 1 when it crosses no pad word (cross = 0), and
+// words idx .. idx + i when it crosses one (cross = 1; the pad repeats a bin
+// of the window). Greedy reads its offset j from st (bits 8..) and sets step when the
+// right neighbour is taken (j then grows by one).
 template <int VAR>
-__device__ __forceinline__ float term_value(const float* buf, int k, int idx, int i, int st,
-                                            bool& step)
+__device__ __forceinline__ float term_value(const float* buf, int k, int idx, int i, int cross,
+                                            int st, bool& step)
 {
     step = false;
     if constexpr (VAR == kFreqbin) {
         return buf[idx];
     } else if constexpr (VAR == kMax) {
-        // the window's bins are read in blocks issued together; the running
-        // maximum scans them in order (with a strict >, only the first bin's
-        // value decides a NaN result, so the grouping changes no bit)
-        float tv = buf[idx];
-        int jj = 1;
-        for (; jj + 8 <= i; jj += 8) {
-            float w[8];
+        // running maximum with a strict >, the window's first bin first: only
+        // that bin decides a NaN result, and repeated later bins leave the
+        // value unchanged. The window is the L = i + cross words from idx; all
+        // of them are read before the maximum is formed, in blocks of 8 whose
+        // last one ends at word L - 1 (overlapping its predecessor rather than
+        // leaving a ragged tail).
+        const float* w = buf + idx;
+        const int L = i + cross;
+        if (L <= 8) {
+            const float x0 = w[0];
+            if (L == 1) return x0;
+            if (L < 4) {
+                const float a1 = w[1], a2 = w[L - 1];
+                float tv = a1 > x0 ? a1 : x0;
+                return a2 > tv ? a2 : tv;
+            }
+            float v[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) w[u] = buf[pidx(k + jj + u)];
+            for (int u = 1; u < 4; ++u) v[u] = w[u];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) tv = w[u] > tv ? w[u] : tv;
+            for (int u = 0; u < 4; ++u) v[4 + u] = w[L - 4 + u];
+            float tv = x0;
+#pragma unroll
+            for (int u = 1; u < 8; ++u) tv = v[u] > tv ? v[u] : tv;
+            return tv;
         }
-        if (jj + 4 <= i) {
-            float w[4];
+        // first round: blocks at words 0 and 8 (when before the last block)
+        // and the last block; second round: blocks at 16 and 24
+        float v[3][8];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) w[u] = buf[pidx(k + jj + u)];
+        for (int u = 0; u < 8; ++u) v[0][u] = w[u];
+        if (L > 16) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) tv = w[u] > tv ? w[u] : tv;
-            jj += 4;
+            for (int u = 0; u < 8; ++u) v[1][u] = w[8 + u];
         }
-        for (; jj < i; ++jj) {
-            const float w = buf[pidx(k + jj)];
-            tv = w > tv ? w : tv;
+        const float* wl = w + (L - 8);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[2][u] = wl[u];
+        float tv = v[0][0];
+#pragma unroll
+        for (int u = 1; u < 8; ++u) tv = v[0][u] > tv ? v[0][u] : tv;
+        if (L > 16) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) tv = v[1][u] > tv ? v[1][u] : tv;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) tv = v[2][u] > tv ? v[2][u] : tv;
+        if (L > 24) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[0][u] = w[16 + u];
+            if (L > 32) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[1][u] = w[24 + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) tv = v[0][u] > tv ? v[0][u] : tv;
+            if (L > 32) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) tv = v[1][u] > tv ? v[1][u] : tv;
+            }
         }
         return tv;
     } else {
         if (i == 1) return buf[idx];
-        const int j = st >> 8;
-        const float x0 = buf[pidx(k + j)];
-        const float x1 = buf[pidx(k + j + 1)];
+        const int q = pidx(k + (st >> 8));
+        const float x0 = buf[q];
+        const float x1 = buf[q + 1];
         step = x1 > x0;
         return step ? x1 : x0;
     }
@@ -465,6 +516,8 @@ __global__ __launch_bounds__(WG) void k_hrms1d_span(const Run1DParams p)
             const int k0 = (int)__umul24((unsigned)i, (unsigned)tid) + i * a - d0.cp;
             const int rstep = i * (WG + WG / 32);
             const int x0 = pidx(k0);
+            // window crossing of a pad word; the same for every r (k0 mod 32 is)
+            const int cross = ((k0 & 31) + i - 1) >> 5;
             const int span = ue - ub;
             const int u0 = tid - ub;   // output offset in the run, block 0
             const bool snap = (i & (i - 1)) == 0;
@@ -474,8 +527,8 @@ __global__ __launch_bounds__(WG) void k_hrms1d_span(const Run1DParams p)
                     bool stp[R];
 #pragma unroll
                     for (int r = 0; r < R; ++r)
-                        tv[r] = term_value<VAR>(buf, k0 + r * i * WG, x0 + r * rstep, i, st[r],
-                                                stp[r]);
+                        tv[r] = term_value<VAR>(buf, k0 + r * i * WG, x0 + r * rstep, i, cross,
+                                                st[r], stp[r]);
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
                         acc[r] = acc[r] + tv[r];
@@ -488,7 +541,7 @@ __global__ __launch_bounds__(WG) void k_hrms1d_span(const Run1DParams p)
                         if ((unsigned)(u0 + r * WG) < (unsigned)span) {
                             bool stp;
                             const float tv = term_value<VAR>(buf, k0 + r * i * WG, x0 + r * rstep,
-                                                             i, st[r], stp);
+                                                             i, cross, st[r], stp);
                             acc[r] = acc[r] + tv;
                             if (stp) st[r] += 256;
                         }
@@ -515,7 +568,7 @@ __global__ __launch_bounds__(WG) void k_hrms1d_span(const Run1DParams p)
                 if (full || (unsigned)(u0 + r * WG) < (unsigned)span) {
                     bool stp;
                     const float tv = term_value<VAR>(buf, k0 + r * i * WG, x0 + r * rstep, i,
-                                                     st[r], stp);
+                                                     cross, st[r], stp);
                     if (stp) st[r] += 256;
                     acc[r] = acc[r] + tv;
                     const float hv = acc[r] * rh;

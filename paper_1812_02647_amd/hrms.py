@@ -115,6 +115,13 @@ def lib():
             raise RuntimeError(
                 f"HIP library {LIB_PATH} is missing: run __graft_entry__.build() "
                 "(or python -m paper_1812_02647_amd.build) first")
+        # PyTorch ships its own copy of the HIP runtime. Loaded after this
+        # library, it finds the runtime that this library pulled in and sees no
+        # device; loading torch first makes both share torch's copy.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         vp, i32 = C.c_void_p, C.c_int
         L.hrms_create.argtypes = [C.POINTER(vp), i32, C.c_char_p]

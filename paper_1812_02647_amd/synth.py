@@ -202,3 +202,76 @@ def plane(nf: int = 1 << 21, zmax: int = 42, seed: int = SEED_BASE + 2, n_comb: 
                 x[zr, k + 1] = np.float32(x[zr, k + 1] + np.float32(a * sinc2(1.0 - d)))
         combs.append((f0, z0))
     return x, combs
+
+
+# ---------------------------------------------------------------------------
+# Simulated pulsar observation (Sec. 3)
+# ---------------------------------------------------------------------------
+
+# 20 s of data sampled every 64 microseconds: 312500 samples, so the power
+# spectrum has 156251 bins of width 1 / 20 s = 0.05 Hz.
+OBS_SECONDS = 20.0
+SAMPLE_SECONDS = 64e-6
+OBS_SAMPLES = 312500
+
+
+def pulsar_time_series(f0_hz: float, amp: float, kappa: float = 20.0, phase: float = 0.0,
+                       seed: int = SEED_BASE + 4, n: int = OBS_SAMPLES,
+                       ts: float = SAMPLE_SECONDS):
+    """Pulse train with a modified von Mises profile exp(kappa (cos(2 pi phi) - 1))
+    (unit peak, duty cycle shrinking with kappa) at frequency f0_hz and peak
+    amplitude amp, plus white Gaussian noise of unit variance (numpy's PCG64
+    generator seeded with ``seed``). Binary64."""
+    t = np.arange(n, dtype=np.float64) * ts
+    prof = np.exp(kappa * (np.cos(2.0 * np.pi * (f0_hz * t + phase)) - 1.0))
+    return amp * prof + np.random.default_rng(seed).standard_normal(n)
+
+
+def pulsar_power_spectrum(f0_hz: float, amp: float, kappa: float = 20.0, phase: float = 0.0,
+                          seed: int = SEED_BASE + 4, n: int = OBS_SAMPLES,
+                          ts: float = SAMPLE_SECONDS):
+    """FP32 power spectrum |X_k|^2 / n, k = 0 .. n/2, of the mean-removed pulsar
+    time series (numpy's real FFT in binary64, then rounded once). Noise bins
+    are exponential with unit mean; the DC bin is zero."""
+    x = pulsar_time_series(f0_hz, amp, kappa, phase, seed, n, ts)
+    x = x - x.mean()
+    X = np.fft.rfft(x)
+    return ((X.real * X.real + X.imag * X.imag) / n).astype(np.float32)
+
+
+def sensitivity_set(k0_list=(150, 400), deltas=tuple(np.arange(8) / 8.0), seeds: int = 3,
+                    amp: float = 0.1, kappa: float = 20.0, seed: int = SEED_BASE + 4):
+    """Spectra for the response across one Fourier bin: pulsars at
+    f0 = (k0 + delta) * 0.05 Hz for every k0, delta and noise draw. Returns
+    ``(x, offsets, meta)``: the packed FP32 spectra and, per spectrum,
+    (k0 + delta, delta, draw)."""
+    df = 1.0 / OBS_SECONDS
+    spectra, meta = [], []
+    for d in deltas:
+        for k0 in k0_list:
+            for r in range(seeds):
+                kf = k0 + float(d)
+                s = seed + 7919 * k0 + 104729 * int(round(float(d) * 1024)) + r
+                spectra.append(pulsar_power_spectrum(kf * df, amp, kappa, 0.0, s))
+                meta.append((kf, float(d), r))
+    offsets = np.zeros(len(spectra) + 1, np.int64)
+    np.cumsum([s.size for s in spectra], out=offsets[1:])
+    return np.concatenate(spectra), offsets, meta
+
+
+def frequency_sweep_set(n_freq: int = 32, lo_hz: float = 2.0, hi_hz: float = 150.0,
+                        amp: float = 0.1, kappa: float = 20.0, seed: int = SEED_BASE + 5):
+    """Spectra for the averaged response: n_freq pulsars at frequencies drawn
+    uniformly in [lo_hz, hi_hz) (any fractional bin offset), one noise draw
+    each. Returns ``(x, offsets, meta)`` with meta[k] = (f0 / 0.05 Hz, frac, 0)."""
+    df = 1.0 / OBS_SECONDS
+    rng = np.random.default_rng(seed)
+    f0s = rng.uniform(lo_hz, hi_hz, n_freq)
+    spectra, meta = [], []
+    for k, f0 in enumerate(f0s):
+        spectra.append(pulsar_power_spectrum(float(f0), amp, kappa, 0.0, seed + 1 + k))
+        kf = float(f0) / df
+        meta.append((kf, kf - math.floor(kf), 0))
+    offsets = np.zeros(len(spectra) + 1, np.int64)
+    np.cumsum([s.size for s in spectra], out=offsets[1:])
+    return np.concatenate(spectra), offsets, meta
