@@ -12,6 +12,8 @@
  *   - Max HRMS, eq. (2), Sec. 2
  *   - freq-bin HRMS, eq. (3), Sec. 2
  *   - Greedy HRMS, eq. (4) and the sentence after it, Sec. 2
+ *   - exhaustive-path ("optimal") sum, named in Sec. 1 as performing every
+ *     possible sum; the reading used here is stated at sum_opt_paths
  *   - 2D harmonic sum after the acceleration search: named in the abstract and
  *     Sec. 1 but not defined; the reading used here is stated at oracle_2d_sum.
  *   - SNR (Sec. 3) is reported but not defined; the reading used here is stated
@@ -49,6 +51,7 @@
 #define OV_MAX 1
 #define OV_FREQBIN 2
 #define OV_GREEDY 3
+#define OV_OPT 4
 
 #define OE_OK 0
 #define OE_INVAL (-1)
@@ -133,6 +136,72 @@ static double sum_greedy(const double* x, int64_t n, int H, int f32)
     return acc;
 }
 
+/*
+ * Exhaustive-path sum. Sec. 1 names an optimal harmonic sum that performs every
+ * possible sum; it is read as the maximum, over every offset path that eq. (4)
+ * could follow, of the sum along that path: j_1 = 0 and j_k = j_{k-1} or
+ * j_{k-1} + 1 for k = 2..H, and
+ *     S_H(n) = max over paths of  x(n) + sum_{k=2..H} x(k*n + j_k).
+ * Each path is summed in the order k = 1..H (in the chosen precision) and the
+ * largest path sum is kept (a later path replaces it only when strictly
+ * larger). Greedy follows one of these paths, so it never exceeds S_H.
+ *
+ * sum_opt_paths is that definition, enumerating the 2^(H-1) paths (bit k-2 of
+ * the path number is the step taken at harmonic k): only practical for small
+ * H. sum_opt is the same maximum by the recurrence over offsets,
+ *     P_1(0) = x(n),
+ *     P_k(j) = max(P_{k-1}(j), P_{k-1}(j-1)) + x(k*n + j),  0 <= j < k,
+ * (a missing predecessor is skipped), S_H = max_j P_H(j). Rounding to binary32
+ * is monotone, so the largest rounded path sum and the recurrence agree
+ * exactly; the pins check the two against each other.
+ */
+static double sum_opt_paths(const double* x, int64_t n, int H, int f32)
+{
+    double best = 0.0;
+    const int64_t npaths = (int64_t)1 << (H - 1);
+    for (int64_t path = 0; path < npaths; ++path) {
+        double acc = x[n];
+        int64_t j = 0;
+        for (int k = 2; k <= H; ++k) {
+            j += (path >> (k - 2)) & 1;
+            acc = rnd(f32, acc + x[(int64_t)k * n + j]);
+        }
+        if (path == 0 || acc > best) best = acc;
+    }
+    return best;
+}
+
+static double sum_opt(const double* x, int64_t n, int H, int f32)
+{
+    double P[32], Q[32];
+    P[0] = x[n];
+    for (int k = 2; k <= H; ++k) {
+        for (int j = 0; j < k; ++j) {
+            double m;
+            if (j == 0) {
+                m = P[0];
+            } else if (j == k - 1) {
+                m = P[k - 2];
+            } else {
+                m = P[j - 1] > P[j] ? P[j - 1] : P[j];
+            }
+            Q[j] = rnd(f32, m + x[(int64_t)k * n + j]);
+        }
+        for (int j = 0; j < k; ++j) P[j] = Q[j];
+    }
+    double best = P[0];
+    for (int j = 1; j < H; ++j)
+        if (P[j] > best) best = P[j];
+    return best;
+}
+
+double oracle_sum_opt_paths(const double* x, int64_t N, int H, int64_t n, int f32)
+{
+    (void)N;
+    if (H < 1 || H > 24) return NAN;
+    return sum_opt_paths(x, n, H, f32);
+}
+
 /* Whether level H of output n exists. eq. (2)-(4) index up to H*n + H - 1, so
  * the level exists when that index is inside the spectrum; eq. (1) never reads
  * past n, so every level exists for every n. */
@@ -150,6 +219,7 @@ double oracle_sum_1d(const double* x, int64_t N, int variant, int H, int64_t n, 
     case OV_MAX: return sum_max(x, n, H, f32);
     case OV_FREQBIN: return sum_freqbin(x, n, H, f32);
     case OV_GREEDY: return sum_greedy(x, n, H, f32);
+    case OV_OPT: return sum_opt(x, n, H, f32);
     default: return NAN;
     }
 }
@@ -266,7 +336,7 @@ int oracle_hrms_1d(const double* x, int64_t N, int variant, int hmax, const int6
                    double* max_snr, uint8_t* best_h)
 {
     int nl = oracle_num_levels(hmax);
-    if (nl < 1 || N < 1 || !x || variant < 0 || variant > 3) return OE_INVAL;
+    if (nl < 1 || N < 1 || !x || variant < 0 || variant > OV_OPT) return OE_INVAL;
     if (!idx) cnt = N;
     for (int64_t k = 0; k < cnt; ++k) {
         int64_t n = idx ? idx[k] : k;

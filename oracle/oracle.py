@@ -16,8 +16,8 @@ import subprocess
 
 import numpy as np
 
-EQ1, MAX, FREQBIN, GREEDY = 0, 1, 2, 3
-VARIANTS = {"eq1": EQ1, "max": MAX, "freqbin": FREQBIN, "greedy": GREEDY}
+EQ1, MAX, FREQBIN, GREEDY, OPT = 0, 1, 2, 3, 4
+VARIANTS = {"eq1": EQ1, "max": MAX, "freqbin": FREQBIN, "greedy": GREEDY, "opt": OPT}
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "hrms_oracle.c")
@@ -47,6 +47,8 @@ def _configure(L):
     L.oracle_snr_consts.argtypes = [i32, d, d, i32, vp, vp, vp, vp]
     L.oracle_sum_1d.argtypes = [vp, i64, i32, i32, i64, i32]
     L.oracle_sum_1d.restype = d
+    L.oracle_sum_opt_paths.argtypes = [vp, i64, i32, i64, i32]
+    L.oracle_sum_opt_paths.restype = d
     L.oracle_sum_2d.argtypes = [vp, i64, i32, i32, i32, i64, i32, i32]
     L.oracle_sum_2d.restype = d
     L.oracle_hrms_1d.argtypes = [vp, i64, i32, i32, vp, i64, vp, vp, i32, vp, vp, vp]
@@ -129,6 +131,12 @@ def sum_1d(x, variant: int, H: int, n: int, f32: bool = False) -> float:
     """Unnormalised S_H(n) straight from the definition."""
     x = _f64(x)
     return lib().oracle_sum_1d(_ptr(x), x.size, variant, H, n, int(f32))
+
+
+def sum_opt_paths(x, H: int, n: int, f32: bool = False) -> float:
+    """Exhaustive-path S_H(n) by enumerating every offset path (H <= 24)."""
+    x = _f64(x)
+    return lib().oracle_sum_opt_paths(_ptr(x), x.size, H, n, int(f32))
 
 
 def sum_2d(x2d, zmax: int, variant: int, H: int, m: int, z: int, f32: bool = False) -> float:

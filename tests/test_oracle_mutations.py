@@ -29,12 +29,12 @@ MUTATIONS = [
      "acc = rnd(f32, acc + x[(int64_t)(i - 1) * n + (i == 1 ? n : 0)]);"),
     ("freqbin drops the fundamental", "for (int i = 1; i <= H; ++i) acc = rnd(f32, acc + x[(int64_t)i * n]);",
      "for (int i = 2; i <= H; ++i) acc = rnd(f32, acc + x[(int64_t)i * n]);"),
-    ("greedy takes ties to the right", "        if (b > a) {\n            acc = rnd(f32, acc + b);\n            j += 1;\n        } else {\n            acc = rnd(f32, acc + a);\n        }\n    }\n    return acc;\n}\n\n/* Whether",
-     "        if (b >= a) {\n            acc = rnd(f32, acc + b);\n            j += 1;\n        } else {\n            acc = rnd(f32, acc + a);\n        }\n    }\n    return acc;\n}\n\n/* Whether"),
-    ("greedy never moves", "            acc = rnd(f32, acc + b);\n            j += 1;\n        } else {\n            acc = rnd(f32, acc + a);\n        }\n    }\n    return acc;\n}\n\n/* Whether",
-     "            acc = rnd(f32, acc + b);\n        } else {\n            acc = rnd(f32, acc + a);\n        }\n    }\n    return acc;\n}\n\n/* Whether"),
-    ("greedy reads harmonic k-1", "        double a = x[(int64_t)k * n + j];\n        double b = x[(int64_t)k * n + j + 1];\n        if (b > a) {\n            acc = rnd(f32, acc + b);\n            j += 1;\n        } else {\n            acc = rnd(f32, acc + a);\n        }\n    }\n    return acc;\n}\n\n/* Whether",
-     "        double a = x[(int64_t)(k - 1) * n + j];\n        double b = x[(int64_t)(k - 1) * n + j + 1];\n        if (b > a) {\n            acc = rnd(f32, acc + b);\n            j += 1;\n        } else {\n            acc = rnd(f32, acc + a);\n        }\n    }\n    return acc;\n}\n\n/* Whether"),
+    ("greedy takes ties to the right", "        if (b > a) {\n            acc = rnd(f32, acc + b);\n            j += 1;\n        } else {\n            acc = rnd(f32, acc + a);\n        }\n    }\n    return acc;\n}\n\n/*\n * Exhaustive-path",
+     "        if (b >= a) {\n            acc = rnd(f32, acc + b);\n            j += 1;\n        } else {\n            acc = rnd(f32, acc + a);\n        }\n    }\n    return acc;\n}\n\n/*\n * Exhaustive-path"),
+    ("greedy never moves", "            acc = rnd(f32, acc + b);\n            j += 1;\n        } else {\n            acc = rnd(f32, acc + a);\n        }\n    }\n    return acc;\n}\n\n/*\n * Exhaustive-path",
+     "            acc = rnd(f32, acc + b);\n        } else {\n            acc = rnd(f32, acc + a);\n        }\n    }\n    return acc;\n}\n\n/*\n * Exhaustive-path"),
+    ("greedy reads harmonic k-1", "        double a = x[(int64_t)k * n + j];\n        double b = x[(int64_t)k * n + j + 1];\n        if (b > a) {\n            acc = rnd(f32, acc + b);\n            j += 1;\n        } else {\n            acc = rnd(f32, acc + a);\n        }\n    }\n    return acc;\n}\n\n/*\n * Exhaustive-path",
+     "        double a = x[(int64_t)(k - 1) * n + j];\n        double b = x[(int64_t)(k - 1) * n + j + 1];\n        if (b > a) {\n            acc = rnd(f32, acc + b);\n            j += 1;\n        } else {\n            acc = rnd(f32, acc + a);\n        }\n    }\n    return acc;\n}\n\n/*\n * Exhaustive-path"),
     ("level domain one too long", "return n < N / H;", "return n <= N / H;"),
     ("scale 1/H instead of 1/sqrt(H)", "return rnd(f32, 1.0 / sqrt((double)H));",
      "return rnd(f32, 1.0 / (double)H);"),
@@ -69,6 +69,12 @@ MUTATIONS = [
      "for (int j = 1; j < i - 1; ++j)\n                if (w[j] > m)"),
     ("2d max reads the fundamental's row", "            const double* w = x + row * ld + (int64_t)i * mbin;",
      "            const double* w = x + (round_half_away((int64_t)z, H) + zmax) * ld + (int64_t)i * mbin;"),
+    ("opt recurrence never steps right", "m = P[j - 1] > P[j] ? P[j - 1] : P[j];", "m = P[j];"),
+    ("opt recurrence keeps the last state", "    double best = P[0];\n    for (int j = 1; j < H; ++j)\n        if (P[j] > best) best = P[j];",
+     "    double best = P[H - 1];"),
+    ("opt paths may step by two", "            j += (path >> (k - 2)) & 1;", "            j += 2 * ((path >> (k - 2)) & 1);"),
+    ("opt paths skip the last harmonic", "        for (int k = 2; k <= H; ++k) {\n            j += (path >> (k - 2)) & 1;",
+     "        for (int k = 2; k < H; ++k) {\n            j += (path >> (k - 2)) & 1;"),
     ("scale uses binary64 1/mu", "double inv = (double)(float)(1.0 / mu);", "double inv = 1.0 / mu;"),
 ]
 

@@ -493,3 +493,54 @@ def test_scale_f32():
     y = O.scale_f32(x, 3.0)
     inv = np.float32(1.0 / 3.0)
     assert np.array_equal(y, (x.astype(np.float32) * inv).astype(np.float64))
+
+
+# --------------------------------------------------------------------------
+# Exhaustive-path sum (the "optimal" sum of Sec. 1 that performs every sum).
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("f32", [False, True])
+def test_opt_recurrence_equals_every_path(f32):
+    rng = np.random.default_rng(11)
+    x = rng.exponential(size=4000)
+    xi = rng.integers(0, 6, size=4000).astype(np.float64)   # many ties
+    for arr in (x, xi):
+        for H in (1, 2, 3, 4, 5, 8, 12, 16):
+            for n in (0, 1, 2, 5, 17, 63, 200):
+                if H * n + H - 1 >= arr.size:
+                    continue
+                assert O.sum_1d(arr, O.OPT, H, n, f32) == O.sum_opt_paths(arr, H, n, f32), (H, n)
+
+
+def test_opt_hand_examples():
+    x = np.zeros(64)
+    n = 10
+    x[10], x[20], x[21], x[30], x[31], x[32] = 1.0, 0.0, 1.0, 10.0, 0.0, 0.0
+    # Greedy steps right at harmonic 2 and then misses the strong bin at 3 n
+    assert O.sum_1d(x, O.GREEDY, 3, n) == 2.0
+    assert O.sum_1d(x, O.OPT, 3, n) == 11.0
+    # H = 1 is the bin itself; H = 2 is the better of the two neighbours
+    assert O.sum_1d(x, O.OPT, 1, n) == 1.0
+    assert O.sum_1d(x, O.OPT, 2, n) == 2.0
+    # a path steps by at most one per harmonic: y(3 n + 2) is reachable only
+    # through y(2 n + 1). Paths: (0,0) 1+5+0, (0,1) 1+5+0, (1,1) 1+0+0,
+    # (1,2) 1+0+7
+    y = np.zeros(64)
+    y[10], y[20], y[32] = 1.0, 5.0, 7.0
+    assert O.sum_1d(y, O.OPT, 3, n) == 8.0
+
+
+def test_opt_between_greedy_freqbin_and_max():
+    # every eq. (3) and eq. (4) path is a candidate path, and every path term
+    # lies inside the eq. (2) window of its harmonic
+    x = synth.single_spectrum(n=1 << 13, seed=21)
+    for f32 in (False, True):
+        ho, _, _, _ = O.hrms_1d(x, O.OPT, 32, f32=f32, want_snr=False)
+        hf, _, _, _ = O.hrms_1d(x, O.FREQBIN, 32, f32=f32, want_snr=False)
+        hg, _, _, _ = O.hrms_1d(x, O.GREEDY, 32, f32=f32, want_snr=False)
+        hm, _, _, _ = O.hrms_1d(x, O.MAX, 32, f32=f32, want_snr=False)
+        v = ~np.isnan(ho)
+        assert np.array_equal(v, ~np.isnan(hg))
+        assert np.all(ho[v] >= hg[v]) and np.all(ho[v] >= hf[v]) and np.all(ho[v] <= hm[v])
+        # strictly better than Greedy somewhere at the deep levels
+        assert np.any(ho[4][v[4]] > hg[4][v[4]])
