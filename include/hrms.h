@@ -11,6 +11,11 @@
  *                                  the larger of x(k n + j), x(k n + j + 1) and
  *                                  moves j up by one when the right bin is
  *                                  strictly larger
+ *   HRMS_OPT      Sec. 1 ("optimal" sum performing every possible sum), 1D,
+ *                                  h only: the largest sum over every offset
+ *                                  path eq. (4) could follow (j_1 = 0, each
+ *                                  later j equal to or one above the previous),
+ *                                  each path added in the order k = 1..H
  *
  * over batches of 1D power spectra (the periodicity search after the FFT,
  * Sec. 1) and over a 2D frequency x fdot plane (the sum that follows the
@@ -61,7 +66,7 @@ extern "C" {
 
 typedef struct hrms_ctx* hrms_handle;
 
-enum { HRMS_EQ1 = 0, HRMS_MAX = 1, HRMS_FREQBIN = 2, HRMS_GREEDY = 3 };
+enum { HRMS_EQ1 = 0, HRMS_MAX = 1, HRMS_FREQBIN = 2, HRMS_GREEDY = 3, HRMS_OPT = 4 };
 
 /* Storage type of the input bins. FP16 and BF16 widen exactly to FP32 before
  * any arithmetic. */
@@ -102,7 +107,9 @@ enum {
 /* A batch of 1D power spectra (DM trials), packed back to back. */
 typedef struct {
     int32_t n_spectra;        /* >= 1 */
-    int32_t variant;          /* HRMS_EQ1 .. HRMS_GREEDY */
+    int32_t variant;          /* HRMS_EQ1 .. HRMS_OPT; HRMS_OPT takes out_mask ==
+                                 HRMS_OUT_H only (no closed-form null, so no SNR:
+                                 other outputs give HRMS_E_UNSUPPORTED) */
     int32_t dtype;            /* HRMS_F32 / HRMS_F16 / HRMS_BF16 */
     int32_t hmax_all;         /* Hmax of every spectrum when hmax == NULL */
     uint32_t out_mask;        /* HRMS_OUT_* bits; 0 computes only the statistics */
@@ -116,7 +123,8 @@ typedef struct {
                                  (COMPUTE) or read (PROVIDED) */
     float* snr_consts;        /* device or NULL: [n_spectra][HRMS_MAX_LEVELS][2]
                                  = (m_H, q_H) of the run's variant, written;
-                                 unused levels are written as 0 */
+                                 unused levels (and every level of HRMS_OPT)
+                                 are written as 0 */
     float* h;                 /* device: compact level planes at the offsets
                                  given by hrms_layout_1d; needed iff OUT_H */
     float* max_snr;           /* device: offsets[n_spectra] floats; iff OUT_MAXSNR */
@@ -217,7 +225,7 @@ int hrms_run_1d(hrms_handle h, const hrms_run1d_args* a, void* hip_stream);
 int hrms_autotune_1d(hrms_handle h, const hrms_run1d_args* a, void* hip_stream, int reps,
                      int32_t* chosen);
 
-/* Harmonic sum of a 2D plane, any variant. */
+/* Harmonic sum of a 2D plane, HRMS_EQ1 .. HRMS_GREEDY (HRMS_OPT: HRMS_E_UNSUPPORTED). */
 int hrms_run_2d(hrms_handle h, const hrms_run2d_args* a, void* hip_stream);
 
 /* Normalise and store FP32 spectra as FP16 / BF16 (precision form of the 1D

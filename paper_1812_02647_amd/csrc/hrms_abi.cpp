@@ -168,11 +168,15 @@ int validate_1d(hrms_ctx* c, const hrms_run1d_args* a, bool device_ptrs)
 {
     if (!a) return fail(c, HRMS_E_INVAL, "args is NULL");
     if (a->n_spectra < 1) return fail(c, HRMS_E_INVAL, "n_spectra must be >= 1");
-    if (a->variant < HRMS_EQ1 || a->variant > HRMS_GREEDY)
-        return fail(c, HRMS_E_INVAL, "variant must be HRMS_EQ1..HRMS_GREEDY");
+    if (a->variant < HRMS_EQ1 || a->variant > HRMS_OPT)
+        return fail(c, HRMS_E_INVAL, "variant must be HRMS_EQ1..HRMS_OPT");
     if (a->dtype < HRMS_F32 || a->dtype > HRMS_BF16)
         return fail(c, HRMS_E_INVAL, "dtype must be HRMS_F32, HRMS_F16 or HRMS_BF16");
     if (a->out_mask & ~15u) return fail(c, HRMS_E_INVAL, "out_mask has unknown bits");
+    if (a->variant == HRMS_OPT && (a->out_mask & ~HRMS_OUT_H))
+        return fail(c, HRMS_E_UNSUPPORTED,
+                    "HRMS_OPT produces h only: its null distribution has no closed form, so "
+                    "there is no SNR, best-H or candidate output");
     if (a->stats_mode != HRMS_STATS_COMPUTE && a->stats_mode != HRMS_STATS_PROVIDED)
         return fail(c, HRMS_E_INVAL, "stats_mode must be COMPUTE or PROVIDED");
     if ((a->out_mask & HRMS_OUT_CAND) && !std::isfinite(a->cand_threshold))
@@ -219,6 +223,8 @@ int validate_2d(hrms_ctx* c, const hrms_run2d_args* a, bool device_ptrs)
     if (a->ld < a->nf) return fail(c, HRMS_E_INVAL, "ld must be >= nf");
     if (levels_of_hmax(a->hmax) < 0)
         return fail(c, HRMS_E_INVAL, "hmax must be a power of two <= 32");
+    if (a->variant == HRMS_OPT)
+        return fail(c, HRMS_E_UNSUPPORTED, "HRMS_OPT is implemented for 1D spectra only");
     if (a->variant < HRMS_EQ1 || a->variant > HRMS_GREEDY)
         return fail(c, HRMS_E_INVAL, "variant must be HRMS_EQ1..HRMS_GREEDY");
     if (a->dtype < HRMS_F32 || a->dtype > HRMS_BF16)
@@ -292,8 +298,9 @@ Shape1D default_shape(int variant)
 {
     // measured on the 1000 x 2^21, Hmax = 32 batch
     if (variant == HRMS_EQ1) return Shape1D{512, 8, 0, 0};
-    if (variant == HRMS_MAX) return Shape1D{512, 8, 8192, 0};
+    if (variant == HRMS_MAX) return Shape1D{256, 8, 0, 0};
     if (variant == HRMS_GREEDY) return Shape1D{512, 8, 0, 0};
+    if (variant == HRMS_OPT) return kOptShape;
     return Shape1D{512, 8, 0, 32};
 }
 
@@ -383,8 +390,10 @@ int build_plan_1d(hrms_ctx* c, const hrms_run1d_args* a, const Shape1D& shape, P
                     const int ht = 1 << l;
                     const bool top = shape.top > 0 && ht >= shape.top;
                     const Shape1D& sh = top ? kTopShape : shape;
-                    const int tt = top ? Ttop : T;
-                    const int64_t terms = a->variant == HRMS_MAX ? (int64_t)ht * (ht + 1) / 2 : ht;
+                    const int tt = top ? Ttop : hrms1d_band_tile(a->variant, shape, ht);
+                    const int64_t terms = a->variant == HRMS_MAX || a->variant == HRMS_OPT
+                                              ? (int64_t)ht * (ht + 1) / 2
+                                              : ht;
                     for (int t0 = lo; t0 < hi; t0 += tt) {
                         const int te = std::min(t0 + tt, hi);
                         int64_t staged = 0;

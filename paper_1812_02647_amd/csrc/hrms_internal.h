@@ -114,6 +114,9 @@ struct Shape1D {
 
 // Launch shape of the LDS form for the top bands of a split launch.
 constexpr Shape1D kTopShape{1024, 8, 16384, 0};
+// The exhaustive-path sum's only launch shape: 256 lanes, 8 outputs per lane
+// taken in sequence, bins read straight from memory.
+constexpr Shape1D kOptShape{256, 8, 0, 0};
 
 // Kernel launchers (hrms_kernels.hip). Return hipSuccess or the launch error.
 hipError_t launch_stats_partial(int dtype, const StatsParams& p, hipStream_t s);
@@ -125,6 +128,22 @@ inline int hrms1d_tile_outputs(int variant, const Shape1D& s)
 {
     (void)variant;
     return s.wg * s.r;
+}
+// eq. (2) and the exhaustive-path sum in the gathered shapes run the window
+// form, whose lanes walk a tile's outputs in sequence: a tile may hold any
+// multiple of wg * 4 outputs.
+inline bool hrms1d_window_form(int variant, const Shape1D& s)
+{
+    return (variant == 1 || variant == 4) && s.chunk == 0;
+}
+// Tile length of a band whose top level is ht: the window form gives its cheap
+// bands longer tiles so that per-tile work (claim, record, barrier) stays
+// small against the bins they cover.
+inline int hrms1d_band_tile(int variant, const Shape1D& s, int ht)
+{
+    const int t = hrms1d_tile_outputs(variant, s);
+    if (!hrms1d_window_form(variant, s)) return t;
+    return ht <= 2 ? 8 * t : ht <= 8 ? 2 * t : t;
 }
 // Resident workgroups per CU of the 1D kernel; 0 (with *err set) on failure.
 int hrms1d_max_blocks_per_cu(int variant, int dtype, const Shape1D& shape, hipError_t* err);

@@ -35,7 +35,7 @@
 namespace hrms {
 namespace {
 
-constexpr int kEq1 = 0, kMax = 1, kFreqbin = 2, kGreedy = 3;
+constexpr int kEq1 = 0, kMax = 1, kFreqbin = 2, kGreedy = 3, kOpt = 4;
 constexpr int kF32 = 0, kF16 = 1, kBF16 = 2;
 
 template <int DT>
@@ -941,6 +941,12 @@ __global__ __launch_bounds__(kStatsWG) void k_stats_partial(const StatsParams p)
 __device__ void level_consts(int variant, double mu, double sigma, int H, double* m_out,
                              double* q_out)
 {
+    if (variant == kOpt) {
+        // the maximum over every path has no closed-form null moments: no SNR
+        *m_out = 0.0;
+        *q_out = 0.0;
+        return;
+    }
     const double rh = sqrt((double)H);
     double mean_s, var_s;
     if (variant == kEq1 || variant == kFreqbin) {
@@ -1009,6 +1015,311 @@ __global__ __launch_bounds__(64) void k_consts(const ConstsParams p)
             p.user_consts[((int64_t)s * kMaxLevels + l) * 2] = m32;
             p.user_consts[((int64_t)s * kMaxLevels + l) * 2 + 1] = q32;
         }
+    }
+}
+
+// --------------------------------------------------------------------------
+// Window form: eq. (2) and the exhaustive-path sum, one output per lane at a
+// time (R outputs per lane taken in sequence), every harmonic's window of k
+// bins x(k n) .. x(k n + k - 1) read straight from memory with the harmonic
+// loop fully unrolled, so that the window's loads are issued together and
+// merged into wide loads.
+//
+// eq. (2): term k is the window's running maximum (strict >, its first bin
+// first), added to the FP32 accumulator in the order k = 1..H.
+//
+// Exhaustive-path sum (the optimal sum named in Sec. 1): the largest sum over
+// every offset path eq. (4) could follow (j_1 = 0, each later offset equal to
+// or one above the previous), by the recurrence over offsets
+//     P_k(j) = max(P_{k-1}(j), P_{k-1}(j-1)) + x(k n + j),  0 <= j < k,
+// with P_1(0) = x(n) and a missing predecessor skipped; level H's sum is the
+// largest P_H(j). Rounding is monotone, so this is the largest FP32 path sum
+// with each path added in the order k = 1..H. The k <= 32 states live in
+// registers. Only h is written (there is no closed-form null for an SNR).
+// --------------------------------------------------------------------------
+// Per-tile values the window form needs, the level constants lane-distributed
+// (lane l holds level l's).
+struct WinTile {
+    __amdgpu_buffer_rsrc_t rs, mrs, brs;
+    int a, tn, ht, spec;
+    float lm, lq, lrh;
+    int lho_lo, lho_hi;
+};
+
+// NR outputs per lane (offsets u0, u0 + stride, ... in the tile) whose top
+// level is at most KMAX, all harmonics unrolled so that every window load of
+// the group is issued before the sums need them. Lanes past the tile's end
+// compute on the tile's first output and their stores fall outside the output
+// ranges, which the buffer resources discard.
+template <int VAR, int DT, int KMAX, int NR, bool CAND>
+__device__ __forceinline__ void win_group(const Run1DParams& p, const WinTile& w, int u0,
+                                          int stride, bool track, CandStage& cands)
+{
+    int nn[NR];
+    float acc[NR], best[NR];
+    int bl[NR];
+    float P[NR][VAR == kOpt ? KMAX : 1];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        const int u = u0 + q * stride;
+        nn[q] = w.a + (u < w.tn ? u : 0);
+        acc[q] = 0.0f;
+        best[q] = 0.0f;
+        bl[q] = 0;
+    }
+#pragma unroll
+    for (int k = 1; k <= KMAX; ++k) {
+        if (k > w.ht) continue;
+        float xv[NR][KMAX];
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+            const int base = k * nn[q];
+#pragma unroll
+            for (int j = 0; j < k; ++j) xv[q][j] = buffer_elem<DT>(w.rs, base + j);
+        }
+        float S[NR];
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+            if constexpr (VAR == kMax) {
+                float tv = xv[q][0];
+#pragma unroll
+                for (int j = 1; j < k; ++j) tv = xv[q][j] > tv ? xv[q][j] : tv;
+                acc[q] = acc[q] + tv;
+                S[q] = acc[q];
+            } else {
+                if (k == 1) {
+                    P[q][0] = xv[q][0];
+                } else {
+                    // top down, so that every update reads the previous states
+                    P[q][k - 1] = P[q][k - 2] + xv[q][k - 1];
+#pragma unroll
+                    for (int j = k - 2; j >= 1; --j) {
+                        const float m = P[q][j - 1] > P[q][j] ? P[q][j - 1] : P[q][j];
+                        P[q][j] = m + xv[q][j];
+                    }
+                    P[q][0] = P[q][0] + xv[q][0];
+                }
+                S[q] = 0.0f;
+                if ((k & (k - 1)) == 0) {
+                    S[q] = P[q][0];
+#pragma unroll
+                    for (int j = 1; j < k; ++j) S[q] = P[q][j] > S[q] ? P[q][j] : S[q];
+                }
+            }
+        }
+        if ((k & (k - 1)) == 0) {
+            const int li = __builtin_ctz((unsigned)k);
+            const float rh = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(w.lrh), li));
+            const int64_t ho =
+                (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane(w.lho_hi, li) << 32) |
+                          (uint32_t)__builtin_amdgcn_readlane(w.lho_lo, li));
+            const __amdgpu_buffer_rsrc_t hrs = out_rsrc(p.h + ho + w.a, w.tn * 4);
+            const float m0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(w.lm), li));
+            const float q0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(w.lq), li));
+#pragma unroll
+            for (int q = 0; q < NR; ++q) {
+                const float hv = S[q] * rh;
+                if (p.out_mask & 1u)
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(hv), hrs,
+                                                          (u0 + q * stride) * 4, 0, 0);
+                if (track) {
+                    const float snr = (hv - m0) * q0;
+                    if (li == 0 || snr > best[q]) {
+                        best[q] = snr;
+                        bl[q] = li;
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        const int u = u0 + q * stride;
+        if (track) {
+            if (p.out_mask & 2u)
+                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(best[q]), w.mrs, u * 4, 0, 0);
+            if (p.out_mask & 4u)
+                __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(1u << bl[q]), w.brs, u, 0, 0);
+        }
+        if constexpr (CAND)
+            append_candidates(p, cands, u < w.tn && best[q] >= p.cand_thr, w.spec, nn[q], best[q],
+                              1 << bl[q]);
+    }
+}
+
+// Words of one wave's staging area in the window form: the 64 windows of a
+// harmonic k <= 32 (64 k bins), one pad word per 32 bins.
+constexpr int kWinWaveWords = 64 * 32 + 64;
+
+// One output per lane of a deep band (top level up to 32). The wave's 64
+// consecutive outputs n0 .. n0 + 63 read, for harmonic k, the contiguous bins
+// k n0 .. k n0 + 64 k - 1: the wave loads them with whole-line accesses into
+// its own LDS area (lane-strided by one bin), then every lane reads its window
+// of k bins from there. Only the wave touches its area, and its LDS accesses
+// are carried out in order, so no barrier is needed. Lanes past the tile's end
+// work on the tile's first output and discard the result.
+template <int VAR, int DT, bool CAND>
+__device__ __forceinline__ void win_deep(const Run1DParams& p, const WinTile& w,
+                                         const __amdgpu_buffer_rsrc_t rs, const int a, const int tn,
+                                         const int ht, int u, bool track, CandStage& cands,
+                                         float* wl)
+{
+    const int lane = (int)threadIdx.x & 63;
+    const int ub = u - lane;   // the wave's first output in the tile
+    if (ub >= tn) return;      // nothing for this wave (uniform)
+    const bool act = u < tn;
+    const int n = a + (act ? u : 0);
+    const int n0 = a + ub;
+    float best = 0.0f;
+    int bl = 0;
+    float P[VAR == kOpt ? 32 : 1];
+    float acc = 0.0f;
+#pragma unroll
+    for (int k = 1; k <= 32; ++k) {
+        if (k <= ht) {
+            {
+                float v[32];
+                const int rbase = k * n0 + lane;
+#pragma unroll
+                for (int t = 0; t < k; ++t) v[t] = buffer_elem<DT>(rs, rbase + 64 * t);
+                __builtin_amdgcn_wave_barrier();   // the previous windows are read
+#pragma unroll
+                for (int t = 0; t < k; ++t) wl[pidx(lane + 64 * t)] = v[t];
+                __builtin_amdgcn_wave_barrier();
+            }
+            float xv[32];
+            const int wb = act ? k * lane : 0;
+#pragma unroll
+            for (int j = 0; j < k; ++j) xv[j] = wl[pidx(wb + j)];
+            float S = 0.0f;
+            if constexpr (VAR == kMax) {
+                float tv = xv[0];
+#pragma unroll
+                for (int j = 1; j < k; ++j) tv = xv[j] > tv ? xv[j] : tv;
+                acc = acc + tv;
+                S = acc;
+            } else {
+                if (k == 1) {
+                    P[0] = xv[0];
+                } else {
+                    // top down, so that every update reads the previous states
+                    P[k - 1] = P[k - 2] + xv[k - 1];
+#pragma unroll
+                    for (int j = k - 2; j >= 1; --j) {
+                        const float m = P[j - 1] > P[j] ? P[j - 1] : P[j];
+                        P[j] = m + xv[j];
+                    }
+                    P[0] = P[0] + xv[0];
+                }
+                if ((k & (k - 1)) == 0) {
+                    S = P[0];
+#pragma unroll
+                    for (int j = 1; j < k; ++j) S = P[j] > S ? P[j] : S;
+                }
+            }
+            if ((k & (k - 1)) == 0) {
+                const int li = __builtin_ctz((unsigned)k);
+                const float rh =
+                    __int_as_float(__builtin_amdgcn_readlane(__float_as_int(w.lrh), li));
+                const float hv = S * rh;
+                if (p.out_mask & 1u) {
+                    const int64_t ho = (int64_t)(
+                        ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(w.lho_hi, li) << 32) |
+                        (uint32_t)__builtin_amdgcn_readlane(w.lho_lo, li));
+                    const __amdgpu_buffer_rsrc_t hrs = out_rsrc(p.h + ho + a, tn * 4);
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(hv), hrs, u * 4, 0, 0);
+                }
+                if (track) {
+                    const float m0 =
+                        __int_as_float(__builtin_amdgcn_readlane(__float_as_int(w.lm), li));
+                    const float q0 =
+                        __int_as_float(__builtin_amdgcn_readlane(__float_as_int(w.lq), li));
+                    const float snr = (hv - m0) * q0;
+                    if (li == 0 || snr > best) {
+                        best = snr;
+                        bl = li;
+                    }
+                }
+            }
+        }
+    }
+    if (track) {
+        if (p.out_mask & 2u)
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(best), w.mrs, u * 4, 0, 0);
+        if (p.out_mask & 4u)
+            __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(1u << bl), w.brs, u, 0, 0);
+    }
+    if constexpr (CAND)
+        append_candidates(p, cands, act && best >= p.cand_thr, w.spec, n, best, 1 << bl);
+}
+
+template <int VAR, int DT, int WG, int R, bool CAND>
+__global__ __launch_bounds__(WG) void k_hrms1d_win(const Run1DParams p)
+{
+    static_assert(VAR == kMax || VAR == kOpt, "window form: eq. (2) and the exhaustive path");
+    static_assert(VAR == kMax || !CAND, "the exhaustive-path sum has no SNR");
+    static_assert(R % 4 == 0, "outputs per lane come in groups of 4");
+    (void)R;
+    const int tid = (int)threadIdx.x;
+    const int lane = tid & 63;
+    const bool track = VAR == kMax && (CAND || (p.out_mask & 6u) != 0);
+    __shared__ int s_claim[2];
+    __shared__ CandStage cands;
+    __shared__ float wlds[WG / 64][kWinWaveWords];
+    float* wl = wlds[tid >> 6];
+    int cq = (int)(blockIdx.x % (unsigned)p.nqueues), visited = 0;
+    if (tid == 0) {
+        s_claim[0] = claim_tile(p, cq, visited);
+        cands.n = 0u;
+    }
+    __syncthreads();
+    int t = uniform(s_claim[0]);
+    WinTile w;
+    w.spec = -1;
+    w.lm = w.lq = w.lrh = 0.0f;
+    w.lho_lo = w.lho_hi = 0;
+    for (int c = 0; t >= 0; ++c) {
+        if (tid == 0) s_claim[(c + 1) & 1] = claim_tile(p, cq, visited);
+        const TileRec ct = ldc(p.tiles + t);
+        w.a = ct.a;
+        w.ht = 1 << (ct.nlev - 1);
+        w.tn = ct.aend - ct.a;
+        if (ct.spec != w.spec) {
+            w.spec = ct.spec;
+            if (lane < kMaxLevels) {
+                const LevelConst lc = p.consts[(int64_t)w.spec * kMaxLevels + lane];
+                w.lm = lc.m;
+                w.lq = lc.q;
+                w.lrh = lc.rh;
+                const int64_t ho = p.spec[w.spec].hoff[lane];
+                w.lho_lo = (int)(uint32_t)ho;
+                w.lho_hi = (int)(ho >> 32);
+            }
+        }
+        w.rs = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)(static_cast<const char*>(p.x) + ct.xoff * Elem<DT>::kBytes), (short)0,
+            ct.n * Elem<DT>::kBytes, kBufferFlags);
+        w.mrs = out_rsrc(p.max_snr + ct.xoff + w.a, w.tn * 4);
+        w.brs = out_rsrc(p.best_h + ct.xoff + w.a, w.tn);
+        // the cheap bands take several outputs per lane at once, the deep ones
+        // one at a time (their windows already keep many loads in flight)
+        // (a tile holds up to 8 R WG outputs in the cheap bands, R WG otherwise)
+        if (w.ht <= 2) {
+#pragma unroll 1
+            for (int u0 = 0; u0 < w.tn; u0 += 4 * WG)
+                win_group<VAR, DT, 2, 4, CAND>(p, w, u0 + tid, WG, track, cands);
+        } else if (w.ht <= 8) {
+#pragma unroll 1
+            for (int u0 = 0; u0 < w.tn; u0 += 2 * WG)
+                win_group<VAR, DT, 8, 2, CAND>(p, w, u0 + tid, WG, track, cands);
+        } else {
+#pragma unroll 1
+            for (int u0 = 0; u0 < w.tn; u0 += WG)
+                win_deep<VAR, DT, CAND>(p, w, w.rs, w.a, w.tn, w.ht, u0 + tid, track, cands, wl);
+        }
+        __syncthreads();
+        if constexpr (CAND) flush_candidates(p, cands, WG);
+        t = uniform(s_claim[(c + 1) & 1]);
     }
 }
 
@@ -1183,7 +1494,9 @@ __global__ __launch_bounds__(kStatsWG) void k_quantize(const QuantParams p)
 template <int VAR, int DT, int WG, int R, int C, bool CAND>
 void* fund_kernel()
 {
-    if constexpr (C == 0)
+    if constexpr (C == 0 && VAR == kMax)
+        return reinterpret_cast<void*>(&k_hrms1d_win<VAR, DT, WG, R, CAND>);
+    else if constexpr (C == 0)
         return reinterpret_cast<void*>(&k_hrms1d_gather<VAR, DT, WG, R, CAND>);
     else
         return reinterpret_cast<void*>(&k_hrms1d_span<VAR, DT, WG, R, C, CAND>);
@@ -1264,8 +1577,24 @@ const ShapeEntry* find_shape(int variant, const Shape1D& s)
     return nullptr;
 }
 
+void* opt_kernel(int dtype)
+{
+    switch (dtype) {
+    case kF32:
+        return reinterpret_cast<void*>(&k_hrms1d_win<kOpt, kF32, kOptShape.wg, kOptShape.r, false>);
+    case kF16:
+        return reinterpret_cast<void*>(&k_hrms1d_win<kOpt, kF16, kOptShape.wg, kOptShape.r, false>);
+    default:
+        return reinterpret_cast<void*>(&k_hrms1d_win<kOpt, kBF16, kOptShape.wg, kOptShape.r, false>);
+    }
+}
+
 void* kernel_for(int variant, int dtype, const Shape1D& s, bool cand = false)
 {
+    if (variant == kOpt) {
+        const bool ok = s.wg == kOptShape.wg && s.r == kOptShape.r && s.chunk == 0 && s.top == 0;
+        return ok && !cand && dtype >= 0 && dtype <= 2 ? opt_kernel(dtype) : nullptr;
+    }
     if (dtype < 0 || dtype > 2 || variant < 0 || variant > 3) return nullptr;
     const ShapeEntry* e = find_shape(variant, s);
     if (!e) return nullptr;
@@ -1305,6 +1634,10 @@ bool hrms1d_shape_supported(int variant, const Shape1D& shape)
 
 int hrms1d_shapes(int variant, Shape1D* out, int cap)
 {
+    if (variant == kOpt) {
+        if (out && cap > 0) out[0] = kOptShape;
+        return 1;
+    }
     // every compiled shape; the gathered forms also split at the top band
     const int fam = variant == kEq1 ? 1 : 0;
     int n = 0;

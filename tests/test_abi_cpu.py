@@ -95,7 +95,7 @@ def layout_status(a):
     (dict(offsets=[0, 10], hmax_all=64), "Hmax"),
     (dict(offsets=[0, 10], hmax_all=0), "Hmax"),
     (dict(offsets=[0, 10, 20], hmax=[8, 12]), "spectrum 1"),
-    (dict(offsets=[0, 10], variant=4), "variant"),
+    (dict(offsets=[0, 10], variant=5), "variant"),
     (dict(offsets=[0, 10], dtype=3), "dtype"),
     (dict(offsets=[0, 10], out_mask=16), "out_mask"),
     (dict(offsets=[0, 10], stats_mode=2), "stats_mode"),
@@ -118,12 +118,12 @@ def test_validation_of_device_pointers_before_any_enqueue():
     assert st == H.HRMS_OK and total > 0
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
 def test_layout_1d(variant):
     lengths = [1, 7, 100, 4097]
     hmax = [1, 4, 32, 16]
     offsets = np.concatenate([[0], np.cumsum(lengths)])
-    a = make_args(offsets, variant=variant, hmax=hmax)
+    a = make_args(offsets, variant=variant, hmax=hmax, out_mask=1 if variant == 4 else 7)
     offs, total = H.hrms_layout_1d(a)
     expect = 0
     for s, (n, hm) in enumerate(zip(lengths, hmax)):
@@ -153,7 +153,7 @@ def test_layout_2d_and_invalid_planes(variant):
     a.reserved = 1
     assert H.lib().hrms_layout_2d(C.byref(a), None, None) == H.HRMS_E_INVAL
     a.reserved = 0
-    a.variant = 4
+    a.variant = 5
     assert H.lib().hrms_layout_2d(C.byref(a), None, None) == H.HRMS_E_INVAL
 
 
@@ -164,3 +164,15 @@ def test_candidate_threshold_must_be_finite():
     assert st == H.HRMS_E_INVAL and "cand_threshold" in H.last_error(None)
     a.cand_threshold = 6.0
     assert layout_status(a)[0] == H.HRMS_OK
+
+
+def test_exhaustive_path_sum_is_h_only_and_1d_only():
+    for mask in (2, 3, 4, 7, 8, 9):
+        a = make_args([0, 100], variant=H.HRMS_OPT, out_mask=mask)
+        assert layout_status(a)[0] == H.HRMS_E_UNSUPPORTED, mask
+        assert "HRMS_OPT" in H.last_error(None)
+    assert layout_status(make_args([0, 100], variant=H.HRMS_OPT, out_mask=1))[0] == H.HRMS_OK
+    assert layout_status(make_args([0, 100], variant=H.HRMS_OPT, out_mask=0))[0] == H.HRMS_OK
+    a = H.hrms_run2d_args()
+    a.nf, a.zmax, a.hmax, a.variant, a.ld, a.out_mask = 1000, 3, 16, H.HRMS_OPT, 1000, 1
+    assert H.lib().hrms_layout_2d(C.byref(a), None, None) == H.HRMS_E_UNSUPPORTED
