@@ -47,7 +47,7 @@ METRIC = "G input bins/s and % of HBM peak, 1D batch Hmax=32, FP32 vs FP16-stora
 HBM_PEAK_GBS = 8000.0
 VARIANT_NAMES = ["eq1", "max", "freqbin", "greedy"]
 # kernels of the default launch shapes
-KERNEL_OF = {"eq1": "k_hrms1d_eq1", "max": "k_hrms1d_span", "freqbin": "k_hrms1d_gather+k_hrms1d_span",
+KERNEL_OF = {"eq1": "k_hrms1d_eq1", "max": "k_hrms1d_win", "freqbin": "k_hrms1d_gather+k_hrms1d_span",
              "greedy": "k_hrms1d_gather"}
 
 
@@ -365,6 +365,24 @@ def workload_batch(args):
         del b
     del sa
 
+    # exhaustive-path sum (h only; not part of the step, which holds the
+    # paper's four variants)
+    ob = H.Batch1D(xd, offsets, H.HRMS_OPT, hmax, out_mask=H.HRMS_OUT_H, stats=stc,
+                   want_consts=False)
+    ob.run(handle)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(max(1, args.steps)):
+        ob.run(handle)
+    e1.record()
+    torch.cuda.synchronize()
+    t_opt = e0.elapsed_time(e1) / max(1, args.steps)
+    opt = {"ms": round(t_opt, 4), "gbins_per_s": round(total / t_opt / 1e6, 2),
+           "outputs": "h only", "kernel": "k_hrms1d_win (exhaustive path)"}
+    del ob, stc
+    torch.cuda.empty_cache()
+
     fp16 = None
     if not args.no_fp16:
         y = torch.empty(total, dtype=torch.float16, device=dev)
@@ -449,6 +467,7 @@ def workload_batch(args):
         "per_variant": per_variant,
         "stats_ms": round(stats_ms, 4),
         "candidates_only": cand,
+        "exhaustive_path": opt,
         "fp16_storage": fp16,
         "wall_s_timed": round(wall, 3),
         "gen_s": round(t_gen, 1),
