@@ -294,12 +294,13 @@ int64_t layout_2d_into(const hrms_run2d_args* a, int64_t* plane_offsets)
 // Plans
 // ---------------------------------------------------------------------------
 
-Shape1D default_shape(int variant)
+Shape1D default_shape(int variant, int dtype)
 {
     // measured on the 1000 x 2^21, Hmax = 32 batch
     if (variant == HRMS_EQ1) return Shape1D{512, 8, 0, 0};
     if (variant == HRMS_MAX) return Shape1D{256, 8, 0, 0};
-    if (variant == HRMS_GREEDY) return Shape1D{512, 8, 0, 0};
+    if (variant == HRMS_GREEDY)   // 2-byte bins halve the lines: more outputs per workgroup pay
+        return dtype == HRMS_F32 ? Shape1D{256, 8, 0, 0} : Shape1D{512, 8, 0, 0};
     if (variant == HRMS_OPT) return kOptShape;
     return Shape1D{512, 8, 0, 32};
 }
@@ -691,7 +692,7 @@ Shape1D shape_for(hrms_ctx* c, const hrms_run1d_args* a)
     }
     auto it = c->tune.find(tune_key(a));
     if (it != c->tune.end() && hrms1d_shape_supported(a->variant, it->second)) return it->second;
-    return default_shape(a->variant);
+    return default_shape(a->variant, a->dtype);
 }
 
 const char* kTuneMagic = "hrms-tune-v2";
