@@ -363,6 +363,20 @@ def workload_batch(args):
         cand[VARIANT_NAMES[v]] = {"ms": round(t, 4), "gbins_per_s": round(total / t / 1e6, 2),
                                   "candidates": b.candidates()[0]}
         del b
+        # local maxima only (max-SNR written, then the peak pass over it)
+        b = H.Batch1D(xd, offsets, v, hmax, out_mask=H.HRMS_OUT_PEAKS | H.HRMS_OUT_MAXSNR,
+                      stats=stc, want_consts=False, cand_capacity=1 << 23, cand_threshold=6.0)
+        b.run(handle)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(max(1, args.steps)):
+            b.run(handle)
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) / max(1, args.steps)
+        cand[VARIANT_NAMES[v]]["peaks_ms"] = round(t, 4)
+        cand[VARIANT_NAMES[v]]["peaks"] = b.candidates()[0]
+        del b
     del sa
 
     # exhaustive-path sum (h only; not part of the step, which holds the

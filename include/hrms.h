@@ -76,8 +76,21 @@ enum { HRMS_F32 = 0, HRMS_F16 = 1, HRMS_BF16 = 2 };
  * maximum SNR over the levels is at least cand_threshold, one hrms_candidate
  * record -- the thresholding step that follows the harmonic sum in a search
  * (Sec. 1) -- fused into the harmonic-sum kernels, so that a run asking only
- * for candidates writes no per-bin output. */
-enum { HRMS_OUT_H = 1u, HRMS_OUT_MAXSNR = 2u, HRMS_OUT_BESTH = 4u, HRMS_OUT_CAND = 8u };
+ * for candidates writes no per-bin output.
+ * HRMS_OUT_PEAKS (1D only; needs HRMS_OUT_MAXSNR, excludes HRMS_OUT_CAND)
+ * appends instead only the bins that are also local maxima of max_snr along
+ * their spectrum: max_snr[n] >= cand_threshold, max_snr[n] > max_snr[n - 1]
+ * and max_snr[n] >= max_snr[n + 1] (a missing neighbour at either end of the
+ * spectrum counts as lower; on a plateau the lowest bin is kept). It runs as
+ * a pass over max_snr after the harmonic sum, since a bin's neighbours may
+ * belong to other tiles. best_h is filled when HRMS_OUT_BESTH is set, else 0. */
+enum {
+    HRMS_OUT_H = 1u,
+    HRMS_OUT_MAXSNR = 2u,
+    HRMS_OUT_BESTH = 4u,
+    HRMS_OUT_CAND = 8u,
+    HRMS_OUT_PEAKS = 16u
+};
 
 /* A candidate bin of a 1D batch. */
 typedef struct {
@@ -130,13 +143,13 @@ typedef struct {
     float* max_snr;           /* device: offsets[n_spectra] floats; iff OUT_MAXSNR */
     uint8_t* best_h;          /* device: offsets[n_spectra] bytes (the H value);
                                  iff OUT_BESTH */
-    hrms_candidate* cand;     /* device: cand_capacity records; iff OUT_CAND. The
+    hrms_candidate* cand;     /* device: cand_capacity records; iff OUT_CAND or OUT_PEAKS. The
                                  order of the records is unspecified. */
-    uint32_t* cand_count;     /* device: one counter, iff OUT_CAND; set to the
+    uint32_t* cand_count;     /* device: one counter, iff OUT_CAND or OUT_PEAKS; set to the
                                  number of candidates found (records past
                                  cand_capacity are dropped, the count is not) */
     uint32_t cand_capacity;   /* records cand can hold (0 allowed: count only) */
-    float cand_threshold;     /* SNR threshold of OUT_CAND (finite) */
+    float cand_threshold;     /* SNR threshold of OUT_CAND / OUT_PEAKS (finite) */
 } hrms_run1d_args;
 
 /* One frequency x fdot plane: row r = z + zmax holds fdot z, z = -zmax..zmax.

@@ -229,6 +229,26 @@ def candidates(max_snr, best_h, threshold: float):
     return sel.astype(np.int64), ms[sel], np.asarray(best_h)[sel]
 
 
+def peaks(max_snr, best_h, threshold: float):
+    """The peak list of one spectrum: the candidates that are also local maxima
+    of the maximum SNR along the spectrum -- max_snr[n] >= threshold,
+    max_snr[n] > max_snr[n - 1] and max_snr[n] >= max_snr[n + 1], a missing
+    neighbour at either end counting as lower (so a plateau keeps its lowest
+    bin) -- in increasing output order, as (bins, snr, best_h) arrays. Written
+    out one bin at a time."""
+    ms = np.asarray(max_snr, dtype=np.float64)
+    bh = np.asarray(best_h)
+    out = []
+    for n in range(ms.size):
+        v = ms[n]
+        lo = ms[n - 1] if n > 0 else -np.inf
+        hi = ms[n + 1] if n + 1 < ms.size else -np.inf
+        if v >= threshold and v > lo and v >= hi:
+            out.append(n)
+    sel = np.array(out, dtype=np.int64)
+    return sel, ms[sel], bh[sel]
+
+
 def scale_f32(x, mu: float):
     """binary32 product x * fl32(1/mu), before narrow rounding."""
     x = _f64(x).ravel()

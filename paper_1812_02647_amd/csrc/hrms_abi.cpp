@@ -172,14 +172,19 @@ int validate_1d(hrms_ctx* c, const hrms_run1d_args* a, bool device_ptrs)
         return fail(c, HRMS_E_INVAL, "variant must be HRMS_EQ1..HRMS_OPT");
     if (a->dtype < HRMS_F32 || a->dtype > HRMS_BF16)
         return fail(c, HRMS_E_INVAL, "dtype must be HRMS_F32, HRMS_F16 or HRMS_BF16");
-    if (a->out_mask & ~15u) return fail(c, HRMS_E_INVAL, "out_mask has unknown bits");
+    if (a->out_mask & ~31u) return fail(c, HRMS_E_INVAL, "out_mask has unknown bits");
+    if ((a->out_mask & HRMS_OUT_PEAKS) && (a->out_mask & HRMS_OUT_CAND))
+        return fail(c, HRMS_E_INVAL, "HRMS_OUT_PEAKS and HRMS_OUT_CAND are exclusive");
+    if ((a->out_mask & HRMS_OUT_PEAKS) && !(a->out_mask & HRMS_OUT_MAXSNR))
+        return fail(c, HRMS_E_INVAL, "HRMS_OUT_PEAKS needs HRMS_OUT_MAXSNR");
     if (a->variant == HRMS_OPT && (a->out_mask & ~HRMS_OUT_H))
         return fail(c, HRMS_E_UNSUPPORTED,
                     "HRMS_OPT produces h only: its null distribution has no closed form, so "
                     "there is no SNR, best-H or candidate output");
     if (a->stats_mode != HRMS_STATS_COMPUTE && a->stats_mode != HRMS_STATS_PROVIDED)
         return fail(c, HRMS_E_INVAL, "stats_mode must be COMPUTE or PROVIDED");
-    if ((a->out_mask & HRMS_OUT_CAND) && !std::isfinite(a->cand_threshold))
+    const bool listing = (a->out_mask & (HRMS_OUT_CAND | HRMS_OUT_PEAKS)) != 0;
+    if (listing && !std::isfinite(a->cand_threshold))
         return fail(c, HRMS_E_INVAL, "cand_threshold must be finite");
     if (!a->offsets) return fail(c, HRMS_E_INVAL, "offsets is NULL");
     if (a->offsets[0] != 0) return fail(c, HRMS_E_INVAL, "offsets[0] must be 0");
@@ -206,9 +211,9 @@ int validate_1d(hrms_ctx* c, const hrms_run1d_args* a, bool device_ptrs)
             return fail(c, HRMS_E_INVAL, "max_snr is NULL but HRMS_OUT_MAXSNR is set");
         if ((a->out_mask & HRMS_OUT_BESTH) && !a->best_h)
             return fail(c, HRMS_E_INVAL, "best_h is NULL but HRMS_OUT_BESTH is set");
-        if ((a->out_mask & HRMS_OUT_CAND) && !a->cand_count)
-            return fail(c, HRMS_E_INVAL, "cand_count is NULL but HRMS_OUT_CAND is set");
-        if ((a->out_mask & HRMS_OUT_CAND) && a->cand_capacity > 0 && !a->cand)
+        if (listing && !a->cand_count)
+            return fail(c, HRMS_E_INVAL, "cand_count is NULL but a candidate list is requested");
+        if (listing && a->cand_capacity > 0 && !a->cand)
             return fail(c, HRMS_E_INVAL, "cand is NULL but cand_capacity > 0");
     }
     return HRMS_OK;
@@ -753,7 +758,7 @@ hipError_t enqueue_1d(const hrms_run1d_args* a, Plan1D* P, const Shape1D& shape,
     cp.consts = (LevelConst*)P->d_consts.p;
     cp.user_consts = a->snr_consts;
     cp.counters = (unsigned int*)P->d_counter.p;
-    cp.cand_count = (a->out_mask & HRMS_OUT_CAND) ? a->cand_count : nullptr;
+    cp.cand_count = (a->out_mask & (HRMS_OUT_CAND | HRMS_OUT_PEAKS)) ? a->cand_count : nullptr;
     cp.n_spec = a->n_spectra;
     cp.variant = a->variant;
     cp.compute_stats = compute ? 1 : 0;
@@ -786,6 +791,19 @@ hipError_t enqueue_1d(const hrms_run1d_args* a, Plan1D* P, const Shape1D& shape,
                 hipSuccess)
                 return e;
         }
+    }
+    if (a->out_mask & HRMS_OUT_PEAKS) {
+        PeakParams pp{};
+        pp.max_snr = a->max_snr;
+        pp.best_h = (a->out_mask & HRMS_OUT_BESTH) ? a->best_h : nullptr;
+        pp.spec = (const SpecDesc*)P->d_spec.p;
+        pp.segs = (const Seg*)P->d_segs.p;
+        pp.cand = reinterpret_cast<CandRec*>(a->cand);
+        pp.cand_count = a->cand_count;
+        pp.cand_cap = a->cand_capacity;
+        pp.thr = a->cand_threshold;
+        pp.nsegs = (int32_t)P->segs.size();
+        if ((e = launch_peaks(pp, stream)) != hipSuccess) return e;
     }
     return hipSuccess;
 }

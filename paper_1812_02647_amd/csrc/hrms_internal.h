@@ -81,6 +81,19 @@ struct Run2DParams {
     int32_t zgroups;            // ceil((2 zmax + 1) / rows per workgroup)
 };
 
+// Local maxima of max_snr above a threshold, one workgroup per segment.
+struct PeakParams {
+    const float* max_snr;
+    const uint8_t* best_h;      // or NULL (records get 0)
+    const SpecDesc* spec;       // xoff, n
+    const Seg* segs;
+    CandRec* cand;
+    unsigned int* cand_count;
+    uint32_t cand_cap;
+    float thr;
+    int32_t nsegs;
+};
+
 // Normalisation constants of the precision form, one per spectrum.
 struct QuantConstParams {
     const SpecDesc* spec;
@@ -152,6 +165,7 @@ bool hrms1d_shape_supported(int variant, const Shape1D& shape);
 // writes up to `cap` of them.
 int hrms1d_shapes(int variant, Shape1D* out, int cap);
 hipError_t launch_hrms2d(int variant, int dtype, const Run2DParams& p, hipStream_t s);
+hipError_t launch_peaks(const PeakParams& p, hipStream_t s);
 hipError_t launch_quant_consts(const QuantConstParams& p, hipStream_t s);
 hipError_t launch_quantize(int dtype, const QuantParams& p, hipStream_t s);
 

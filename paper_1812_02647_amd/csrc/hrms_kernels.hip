@@ -1433,6 +1433,46 @@ __global__ __launch_bounds__(64 * kZRows) void k_hrms2d(const Run2DParams p)
 }
 
 // --------------------------------------------------------------------------
+// Local maxima of max_snr: bin n of a spectrum is listed when
+// max_snr[n] >= thr, max_snr[n] > max_snr[n - 1] and max_snr[n] >= max_snr[n + 1]
+// (a missing neighbour counts as lower). One workgroup per 64K-bin segment;
+// each wavefront claims its records' places with one atomic.
+// --------------------------------------------------------------------------
+constexpr int kPeakWG = 256;
+
+__global__ __launch_bounds__(kPeakWG) void k_peaks(const PeakParams p)
+{
+    const Seg sg = p.segs[blockIdx.x];
+    const SpecDesc sd = p.spec[sg.spec];
+    const float* ms = p.max_snr + sd.ooff;
+    const int lane = (int)threadIdx.x & 63;
+    for (int b = 0; b < sg.len; b += kPeakWG) {
+        const int n = sg.start + b + (int)threadIdx.x;
+        bool take = false;
+        float v = 0.0f;
+        if (n < sg.start + sg.len) {
+            v = ms[n];
+            const float lo = n > 0 ? ms[n - 1] : -INFINITY;
+            const float hi = n + 1 < sd.n ? ms[n + 1] : -INFINITY;
+            take = v >= p.thr && v > lo && v >= hi;
+        }
+        const uint64_t m = __ballot(take);
+        if (m == 0) continue;
+        const int leader = __ffsll((unsigned long long)m) - 1;
+        unsigned int base = 0;
+        if (lane == leader) base = atomicAdd(p.cand_count, (unsigned int)__popcll(m));
+        base = (unsigned int)__shfl((int)base, leader, 64);
+        if (take) {
+            const unsigned int k = base + (unsigned int)__popcll(m & ((1ull << lane) - 1ull));
+            if (k < p.cand_cap) {
+                const int bh = p.best_h ? (int)p.best_h[sd.ooff + n] : 0;
+                p.cand[k] = CandRec{sg.spec, n, v, bh};
+            }
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
 // Precision form: y = round_to_dtype(x * fl32(1 / mu)), round to nearest
 // even; FP16 saturates at +-65504.
 // --------------------------------------------------------------------------
@@ -1713,6 +1753,13 @@ hipError_t launch_hrms2d(int variant, int dtype, const Run2DParams& p, hipStream
     default: return hipErrorInvalidValue;
     }
     hipLaunchKernelGGL(k, grid, block, 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_peaks(const PeakParams& p, hipStream_t s)
+{
+    if (p.nsegs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_peaks, dim3(p.nsegs), dim3(kPeakWG), 0, s, p);
     return hipGetLastError();
 }
 

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libhrms.so")
 
 HRMS_EQ1, HRMS_MAX, HRMS_FREQBIN, HRMS_GREEDY, HRMS_OPT = 0, 1, 2, 3, 4
 HRMS_F32, HRMS_F16, HRMS_BF16 = 0, 1, 2
-HRMS_OUT_H, HRMS_OUT_MAXSNR, HRMS_OUT_BESTH, HRMS_OUT_CAND = 1, 2, 4, 8
+HRMS_OUT_H, HRMS_OUT_MAXSNR, HRMS_OUT_BESTH, HRMS_OUT_CAND, HRMS_OUT_PEAKS = 1, 2, 4, 8, 16
 HRMS_OUT_ALL = 7
 HRMS_STATS_COMPUTE, HRMS_STATS_PROVIDED = 0, 1
 HRMS_OK, HRMS_E_INVAL, HRMS_E_UNSUPPORTED, HRMS_E_NODEVICE, HRMS_E_NOMEM, HRMS_E_HIP = (
@@ -286,13 +286,13 @@ class Batch1D:
         self.best_h = torch.empty(total, dtype=torch.uint8, device=dev) \
             if out_mask & HRMS_OUT_BESTH else None
         # candidate list: records of 4 int32 words (spectrum, bin, snr bits, best H)
+        listing = (out_mask & (HRMS_OUT_CAND | HRMS_OUT_PEAKS)) != 0
         self.cand = torch.zeros((max(cand_capacity, 1), 4), dtype=torch.int32, device=dev) \
-            if out_mask & HRMS_OUT_CAND else None
-        self.cand_count = torch.zeros(1, dtype=torch.int32, device=dev) \
-            if out_mask & HRMS_OUT_CAND else None
+            if listing else None
+        self.cand_count = torch.zeros(1, dtype=torch.int32, device=dev) if listing else None
         a.cand = self.cand.data_ptr() if self.cand is not None else None
         a.cand_count = self.cand_count.data_ptr() if self.cand_count is not None else None
-        a.cand_capacity = cand_capacity if out_mask & HRMS_OUT_CAND else 0
+        a.cand_capacity = cand_capacity if listing else 0
         a.cand_threshold = cand_threshold
         a.stats = self.stats.data_ptr()
         a.snr_consts = self.consts.data_ptr() if self.consts is not None else None

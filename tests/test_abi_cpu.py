@@ -97,7 +97,9 @@ def layout_status(a):
     (dict(offsets=[0, 10, 20], hmax=[8, 12]), "spectrum 1"),
     (dict(offsets=[0, 10], variant=5), "variant"),
     (dict(offsets=[0, 10], dtype=3), "dtype"),
-    (dict(offsets=[0, 10], out_mask=16), "out_mask"),
+    (dict(offsets=[0, 10], out_mask=32), "out_mask"),
+    (dict(offsets=[0, 10], out_mask=16 | 1), "HRMS_OUT_MAXSNR"),
+    (dict(offsets=[0, 10], out_mask=16 | 8 | 2), "exclusive"),
     (dict(offsets=[0, 10], stats_mode=2), "stats_mode"),
 ])
 def test_validation_errors(bad, msg):

@@ -544,3 +544,19 @@ def test_opt_between_greedy_freqbin_and_max():
         assert np.all(ho[v] >= hg[v]) and np.all(ho[v] >= hf[v]) and np.all(ho[v] <= hm[v])
         # strictly better than Greedy somewhere at the deep levels
         assert np.any(ho[4][v[4]] > hg[4][v[4]])
+
+
+def test_peaks_hand_example():
+    nan = float("nan")
+    ms = np.array([7.0, 6.0, 6.5, 9.0, 9.0, 8.0, 5.0, 6.5, 6.5, nan, 6.2, 10.0])
+    bh = np.arange(ms.size, dtype=np.uint8)
+    bins, snr, h = O.peaks(ms, bh, 6.0)
+    # 0: edge, above its right neighbour; 2: below 3; 3: plateau start kept,
+    # 4: equal to its left neighbour, dropped; 7: left of an equal bin kept;
+    # 8: equal to 7 on the left, dropped; 9: NaN never; 10: its left is NaN
+    # (not lower) so it is dropped; 11: right edge, above 10
+    assert list(bins) == [0, 3, 7, 11]
+    assert list(h) == [0, 3, 7, 11] and list(snr) == [7.0, 9.0, 6.5, 10.0]
+    # every peak is a candidate
+    cb, _, _ = O.candidates(ms, bh, 6.0)
+    assert set(bins) <= set(cb)
