@@ -312,9 +312,23 @@ def storage_diff(H, handle, xd, offsets, hmax, variants, n_sub):
         ref, got = b32.h[:n], b16.h[:n]
         err = (got - ref).abs()
         normal = ref.abs() >= 2.0 ** -14          # FP16's normal range
+        # candidate lists at SNR >= 6 from the two storage forms
+        lists = []
+        for xx, sto in ((xn, so), (y, so)):
+            c = H.Batch1D(xx, sub, v, hmax, out_mask=H.HRMS_OUT_CAND, stats=sto.clone(),
+                          want_consts=False, cand_capacity=1 << 20, cand_threshold=6.0)
+            c.run(handle)
+            torch.cuda.synchronize()
+            _, rec = c.candidates()
+            lists.append({(int(r["spectrum"]), int(r["bin"])): int(r["best_h"]) for r in rec})
+        a32, a16 = lists
+        both = set(a32) & set(a16)
         out[VARIANT_NAMES[v]] = {
             "max_abs": float(f"{float(err.max()):.3g}"),
             "max_rel_fp16_normal": float(f"{float((err[normal] / ref[normal].abs()).max()):.3g}"),
+            "cand_snr6_fp32": len(a32), "cand_snr6_fp16": len(a16),
+            "cand_jaccard": round(len(both) / max(1, len(set(a32) | set(a16))), 4),
+            "cand_best_h_agree": round(sum(a32[k] == a16[k] for k in both) / max(1, len(both)), 4),
         }
     return out
 

@@ -1343,11 +1343,23 @@ __device__ __forceinline__ int row_of(int iz, int l)
     return iz >= 0 ? (2 * iz + H) >> (l + 1) : -((-2 * iz + H) >> (l + 1));
 }
 
+// A row of the plane as a buffer resource spanning its nf bins (reads past
+// the row return 0; none is made).
+template <int DT>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_row(const Run2DParams& p, int row)
+{
+    const char* base = static_cast<const char*>(p.x) + (int64_t)row * p.ld * Elem<DT>::kBytes;
+    return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, p.nf * Elem<DT>::kBytes,
+                                             kBufferFlags);
+}
+
 template <int VAR, int DT>
 __global__ __launch_bounds__(64 * kZRows) void k_hrms2d(const Run2DParams p)
 {
     const int lane = (int)threadIdx.x & 63;
-    const int zl = (int)threadIdx.x >> 6;
+    // the fdot row is the same for the whole wavefront, so every row a
+    // harmonic reads is a scalar and its loads go through a scalar resource
+    const int zl = uniform((int)threadIdx.x >> 6);
     const int zg = (int)(blockIdx.x % (unsigned)p.zgroups);
     const int mb = (int)(blockIdx.x / (unsigned)p.zgroups);
     const int rows = 2 * p.zmax + 1;
@@ -1355,7 +1367,6 @@ __global__ __launch_bounds__(64 * kZRows) void k_hrms2d(const Run2DParams p)
     const int m = mb * 64 + lane;
     if (r >= rows || m >= p.nf) return;
     const int z = r - p.zmax;
-    const int64_t ld = p.ld;
     float best = 0.0f;
     int bl = 0;
 #pragma unroll
@@ -1368,45 +1379,53 @@ __global__ __launch_bounds__(64 * kZRows) void k_hrms2d(const Run2DParams p)
 #pragma unroll
                 for (int i = 1; i <= (1 << (kMaxLevels - 1)); ++i) {
                     if (i <= H) {
-                        const int row = row_of(i * z, l) + p.zmax;
-                        const int64_t col = ((int64_t)(2 * i) * m + H) >> (l + 1);
-                        acc = acc + load_scalar<DT>(p.x, (int64_t)row * ld + col);
+                        const auto rs = plane_row<DT>(p, row_of(i * z, l) + p.zmax);
+                        const int col = (int)(((int64_t)(2 * i) * m + H) >> (l + 1));
+                        acc = acc + buffer_elem<DT>(rs, col);
                     }
                 }
             } else if constexpr (VAR == kMax) {
+                // one harmonic at a time (unrolling the harmonics would hold
+                // every window in registers at once); each window is read in
+                // blocks of 4 adjacent bins
+#pragma unroll 1
+                for (int i = 1; i <= H; ++i) {
+                    const auto rs = plane_row<DT>(p, row_of(i * z, l) + p.zmax);
+                    const int base = i * m;
+                    // running maximum in window order with a strict >, as eq. (2)
+                    float w = buffer_elem<DT>(rs, base);
+                    int j = 1;
+                    for (; j + 4 <= i; j += 4) {
+                        float v[4];
 #pragma unroll
-                for (int i = 1; i <= (1 << (kMaxLevels - 1)); ++i) {
-                    if (i <= H) {
-                        const int row = row_of(i * z, l) + p.zmax;
-                        const int64_t base = (int64_t)row * ld + (int64_t)i * m;
-                        // running maximum in window order with a strict >, as eq. (2)
-                        float w = load_scalar<DT>(p.x, base);
-                        for (int j = 1; j < i; ++j) {
-                            const float v = load_scalar<DT>(p.x, base + j);
-                            w = v > w ? v : w;
-                        }
-                        acc = acc + w;
+                        for (int u = 0; u < 4; ++u) v[u] = buffer_elem<DT>(rs, base + j + u);
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) w = v[u] > w ? v[u] : w;
                     }
+                    for (; j < i; ++j) {
+                        const float v = buffer_elem<DT>(rs, base + j);
+                        w = v > w ? v : w;
+                    }
+                    acc = acc + w;
                 }
             } else if constexpr (VAR == kFreqbin) {
 #pragma unroll
                 for (int i = 1; i <= (1 << (kMaxLevels - 1)); ++i) {
                     if (i <= H) {
-                        const int row = row_of(i * z, l) + p.zmax;
-                        acc = acc + load_scalar<DT>(p.x, (int64_t)row * ld + (int64_t)i * m);
+                        const auto rs = plane_row<DT>(p, row_of(i * z, l) + p.zmax);
+                        acc = acc + buffer_elem<DT>(rs, i * m);
                     }
                 }
             } else {
-                const int row1 = row_of(z, l) + p.zmax;
-                acc = load_scalar<DT>(p.x, (int64_t)row1 * ld + m);
+                acc = buffer_elem<DT>(plane_row<DT>(p, row_of(z, l) + p.zmax), m);
                 int j = 0;
 #pragma unroll
                 for (int k = 2; k <= (1 << (kMaxLevels - 1)); ++k) {
                     if (k <= H) {
-                        const int row = row_of(k * z, l) + p.zmax;
-                        const int64_t base = (int64_t)row * ld + (int64_t)k * m + j;
-                        const float x0 = load_scalar<DT>(p.x, base);
-                        const float x1 = load_scalar<DT>(p.x, base + 1);
+                        const auto rs = plane_row<DT>(p, row_of(k * z, l) + p.zmax);
+                        const int q = k * m + j;
+                        const float x0 = buffer_elem<DT>(rs, q);
+                        const float x1 = buffer_elem<DT>(rs, q + 1);
                         if (x1 > x0) {
                             acc = acc + x1;
                             j += 1;
