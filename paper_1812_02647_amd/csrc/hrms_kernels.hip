@@ -696,15 +696,21 @@ __global__ __launch_bounds__(WG) void k_hrms1d_eq1(const Run1DParams p)
             best[r] = 0.0f;
             bl[r] = 0;
         }
+        // stores through resources spanning the tile's outputs: a lane past
+        // the tile's end stores out of range, which the resource discards
+        const int tn = aend - a;
 #pragma unroll
         for (int l = 0; l < kMaxLevels; ++l) {
             if (l < nl) {
                 const LevelConst c = ldc(p.consts + (int64_t)ct.spec * kMaxLevels + l);
                 const int64_t ho = ldc(p.spec[ct.spec].hoff + l);
+                const __amdgpu_buffer_rsrc_t hrs = out_rsrc(p.h + ho + a, tn * 4);
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const float hv = acc[r][l] * c.rh;
-                    if (act[r] && (p.out_mask & 1u)) p.h[ho + nn[r]] = hv;
+                    if (p.out_mask & 1u)
+                        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(hv), hrs, tid * 4,
+                                                              r * WG * 4, 0);
                     const float snr = (hv - c.m) * c.q;
                     if (l == 0 || snr > best[r]) {
                         best[r] = snr;
@@ -713,12 +719,15 @@ __global__ __launch_bounds__(WG) void k_hrms1d_eq1(const Run1DParams p)
                 }
             }
         }
+        const __amdgpu_buffer_rsrc_t mrs = out_rsrc(p.max_snr + ct.xoff + a, tn * 4);
+        const __amdgpu_buffer_rsrc_t brs = out_rsrc(p.best_h + ct.xoff + a, tn);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            if (act[r]) {
-                if (p.out_mask & 2u) p.max_snr[ct.xoff + nn[r]] = best[r];
-                if (p.out_mask & 4u) p.best_h[ct.xoff + nn[r]] = (uint8_t)(1u << bl[r]);
-            }
+            if (p.out_mask & 2u)
+                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(best[r]), mrs, tid * 4,
+                                                      r * WG * 4, 0);
+            if (p.out_mask & 4u)
+                __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(1u << bl[r]), brs, tid, r * WG, 0);
             if constexpr (CAND)
                 append_candidates(p, cands, act[r] && best[r] >= p.cand_thr, ct.spec, nn[r],
                                   best[r], 1 << bl[r]);
