@@ -1464,16 +1464,23 @@ __global__ __launch_bounds__(64 * kZRows) void k_hrms2d(const Run2DParams p)
 // Local maxima of max_snr: bin n of a spectrum is listed when
 // max_snr[n] >= thr, max_snr[n] > max_snr[n - 1] and max_snr[n] >= max_snr[n + 1]
 // (a missing neighbour counts as lower). One workgroup per 64K-bin segment;
-// each wavefront claims its records' places with one atomic.
+// records are gathered in LDS and written with one global atomic per
+// workgroup, as in the fused candidate output.
 // --------------------------------------------------------------------------
 constexpr int kPeakWG = 256;
 
-__global__ __launch_bounds__(kPeakWG) void k_peaks(const PeakParams p)
+__global__ __launch_bounds__(kPeakWG) void k_peaks(const PeakParams pp)
 {
-    const Seg sg = p.segs[blockIdx.x];
-    const SpecDesc sd = p.spec[sg.spec];
-    const float* ms = p.max_snr + sd.ooff;
-    const int lane = (int)threadIdx.x & 63;
+    __shared__ CandStage cands;
+    Run1DParams p{};   // only the candidate-list fields are used
+    p.cand = pp.cand;
+    p.cand_count = pp.cand_count;
+    p.cand_cap = pp.cand_cap;
+    if (threadIdx.x == 0) cands.n = 0u;
+    __syncthreads();
+    const Seg sg = pp.segs[blockIdx.x];
+    const SpecDesc sd = pp.spec[sg.spec];
+    const float* ms = pp.max_snr + sd.ooff;
     for (int b = 0; b < sg.len; b += kPeakWG) {
         const int n = sg.start + b + (int)threadIdx.x;
         bool take = false;
@@ -1482,22 +1489,13 @@ __global__ __launch_bounds__(kPeakWG) void k_peaks(const PeakParams p)
             v = ms[n];
             const float lo = n > 0 ? ms[n - 1] : -INFINITY;
             const float hi = n + 1 < sd.n ? ms[n + 1] : -INFINITY;
-            take = v >= p.thr && v > lo && v >= hi;
+            take = v >= pp.thr && v > lo && v >= hi;
         }
-        const uint64_t m = __ballot(take);
-        if (m == 0) continue;
-        const int leader = __ffsll((unsigned long long)m) - 1;
-        unsigned int base = 0;
-        if (lane == leader) base = atomicAdd(p.cand_count, (unsigned int)__popcll(m));
-        base = (unsigned int)__shfl((int)base, leader, 64);
-        if (take) {
-            const unsigned int k = base + (unsigned int)__popcll(m & ((1ull << lane) - 1ull));
-            if (k < p.cand_cap) {
-                const int bh = p.best_h ? (int)p.best_h[sd.ooff + n] : 0;
-                p.cand[k] = CandRec{sg.spec, n, v, bh};
-            }
-        }
+        const int bh = take && pp.best_h ? (int)pp.best_h[sd.ooff + n] : 0;
+        append_candidates(p, cands, take, sg.spec, n, v, bh);
     }
+    __syncthreads();
+    flush_candidates(p, cands, kPeakWG);
 }
 
 // --------------------------------------------------------------------------
