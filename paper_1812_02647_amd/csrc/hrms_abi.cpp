@@ -429,9 +429,28 @@ int build_plan_1d(hrms_ctx* c, const hrms_run1d_args* a, const Shape1D& shape, P
             tot[x.top] += x.cost;
         }
         for (int part = 0; part < 2; ++part) {
-            std::stable_sort(per_spec[part][s].begin(), per_spec[part][s].end(),
-                             [](const std::pair<int64_t, TileRec>& x,
-                                const std::pair<int64_t, TileRec>& y) { return x.first > y.first; });
+            if (a->variant == HRMS_GREEDY && a->dtype == HRMS_F32) {
+                // FP32 Greedy: tiles in the order of where their top harmonic
+                // reads (a * Ht), deepest band first on ties, so that tiles of
+                // different bands that read the same lines run together
+                // (measured 24.3 -> 22.6 ms on the 1D batch; the other
+                // variants, and Greedy on 2-byte bins, were as fast or faster
+                // in cost order)
+                std::stable_sort(per_spec[part][s].begin(), per_spec[part][s].end(),
+                                 [](const std::pair<int64_t, TileRec>& x,
+                                    const std::pair<int64_t, TileRec>& y) {
+                                     const int64_t gx = (int64_t)x.second.a << (x.second.nlev - 1);
+                                     const int64_t gy = (int64_t)y.second.a << (y.second.nlev - 1);
+                                     if (gx != gy) return gx < gy;
+                                     return x.second.nlev > y.second.nlev;
+                                 });
+            } else {
+                std::stable_sort(per_spec[part][s].begin(), per_spec[part][s].end(),
+                                 [](const std::pair<int64_t, TileRec>& x,
+                                    const std::pair<int64_t, TileRec>& y) {
+                                     return x.first > y.first;
+                                 });
+            }
             spec_cost[part][s] = {tot[part], s};
         }
     }
