@@ -62,6 +62,9 @@ def parse():
     ap.add_argument("--hmax", type=int, default=32)
     ap.add_argument("--variants", default="eq1,max,freqbin,greedy")
     ap.add_argument("--no-fp16", action="store_true", help="skip the FP16-storage form")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the candidate, peak and exhaustive-path timings (only the step's "
+                         "launches run, e.g. for a kernel trace whose means match per_variant)")
     ap.add_argument("--cpu-baseline-spectra", type=int, default=400,
                     help="spectra in the oracle's timed sample (0 skips it)")
     ap.add_argument("--cpu-threads", type=int, default=0, help="0: min(16, cores)")
@@ -71,7 +74,9 @@ def parse():
     return ap.parse_args()
 
 
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1812_02647_amd", "csrc", "hrms_kernels.hip")
+# the kernels and the host planner (tile order, launch shapes) both decide the traffic
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1812_02647_amd", "csrc", f)
+                  for f in ("hrms_kernels.hip", "hrms_abi.cpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
@@ -84,7 +89,7 @@ def measured_traffic(kernel: str, variant: str):
         rec = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
-    digest = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    digest = hashlib.sha256(b"".join(open(f, "rb").read() for f in KERNEL_SOURCES)).hexdigest()
     for ent in rec.get("kernels", []):
         if ent.get("source_sha256") == digest and ent.get("variant") == variant:
             return ent["read_bytes"] + ent["write_bytes"]
@@ -333,32 +338,9 @@ def storage_diff(H, handle, xd, offsets, hmax, variants, n_sub):
     return out
 
 
-def workload_batch(args):
+def extras(args, H, handle, xd, offsets, hmax, variants, total):
+    """Candidate list, peak list and exhaustive-path timings on the batch."""
     import torch
-    from paper_1812_02647_amd import hrms as H
-    from paper_1812_02647_amd import synth
-
-    variants = [VARIANT_NAMES.index(v) for v in args.variants.split(",")]
-    ns, nb, hmax = args.n_spectra, args.n_bins, args.hmax
-    t0 = time.perf_counter()
-    x, offsets, combs = synth.batch(ns, nb, seed=synth.SEED_BASE + 1)
-    t_gen = time.perf_counter() - t0
-    dev = torch.device("cuda", 0)
-    xd = torch.from_numpy(x).to(dev)
-    total = int(offsets[-1])
-    handle = H.hrms_create(0)
-
-    r32 = Runner(H, handle, xd, offsets, hmax, variants, H.HRMS_F32)
-    ms_per_step, stats_ms, per_variant, wall = r32.measure(args.steps, args.warmup)
-    copy_gbs = copy_ceiling(xd)
-    for v in per_variant.values():
-        v["frac_copy"] = round(v["achieved_gbs"] / copy_gbs, 4)
-    dom = max(per_variant, key=lambda k: per_variant[k]["ms"])
-    d = per_variant[dom]
-    del r32
-    torch.cuda.empty_cache()
-
-    # candidate-only form (HRMS_OUT_CAND, SNR >= 6): no per-bin output
     cand = {}
     sa = H.Batch1D(xd, offsets, variants[0], hmax, out_mask=0, want_consts=False).run(handle)
     stc = sa.stats   # statistics computed once, provided to every candidate run
@@ -410,6 +392,40 @@ def workload_batch(args):
            "outputs": "h only", "kernel": "k_hrms1d_win (exhaustive path)"}
     del ob, stc
     torch.cuda.empty_cache()
+
+    return cand, opt
+
+
+def workload_batch(args):
+    import torch
+    from paper_1812_02647_amd import hrms as H
+    from paper_1812_02647_amd import synth
+
+    variants = [VARIANT_NAMES.index(v) for v in args.variants.split(",")]
+    ns, nb, hmax = args.n_spectra, args.n_bins, args.hmax
+    t0 = time.perf_counter()
+    x, offsets, combs = synth.batch(ns, nb, seed=synth.SEED_BASE + 1)
+    t_gen = time.perf_counter() - t0
+    dev = torch.device("cuda", 0)
+    xd = torch.from_numpy(x).to(dev)
+    total = int(offsets[-1])
+    handle = H.hrms_create(0)
+
+    r32 = Runner(H, handle, xd, offsets, hmax, variants, H.HRMS_F32)
+    ms_per_step, stats_ms, per_variant, wall = r32.measure(args.steps, args.warmup)
+    copy_gbs = copy_ceiling(xd)
+    for v in per_variant.values():
+        v["frac_copy"] = round(v["achieved_gbs"] / copy_gbs, 4)
+    dom = max(per_variant, key=lambda k: per_variant[k]["ms"])
+    d = per_variant[dom]
+    del r32
+    torch.cuda.empty_cache()
+
+    # candidate list, peak list and exhaustive path, outside the step
+    cand = {}
+    opt = None
+    if not args.no_extras:
+        cand, opt = extras(args, H, handle, xd, offsets, hmax, variants, total)
 
     fp16 = None
     if not args.no_fp16:
