@@ -403,6 +403,23 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t out_rsrc(const void* base, int
                                              kBufferFlags);
 }
 
+// Output stores carry the non-temporal hint (cache policy NT): the sums and
+// SNR planes are written once and never read back by the launch, so they
+// should not displace the input lines that later tiles read again.
+constexpr int kStreamStore = 2;
+
+__device__ __forceinline__ void stream_store_b32(uint32_t v, __amdgpu_buffer_rsrc_t rs, int voff,
+                                                 int soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(v, rs, voff, soff, kStreamStore);
+}
+
+__device__ __forceinline__ void stream_store_b8(uint8_t v, __amdgpu_buffer_rsrc_t rs, int voff,
+                                                int soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b8(v, rs, voff, soff, kStreamStore);
+}
+
 template <int VAR, int DT, int WG, int R, int CB, bool CAND>
 __global__ __launch_bounds__(WG) void k_hrms1d_span(const Run1DParams p)
 {
@@ -573,8 +590,8 @@ __global__ __launch_bounds__(WG) void k_hrms1d_span(const Run1DParams p)
                     acc[r] = acc[r] + tv;
                     const float hv = acc[r] * rh;
                     if (p.out_mask & 1u)
-                        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(hv), hrs, tid * 4,
-                                                              r * WG * 4, 0);
+                        stream_store_b32(__float_as_uint(hv), hrs, tid * 4,
+                                                              r * WG * 4);
                     if (track) {
                         const float snr = (hv - m0) * q0;
                         if (li == 0 || snr > best[r]) {
@@ -583,11 +600,11 @@ __global__ __launch_bounds__(WG) void k_hrms1d_span(const Run1DParams p)
                         }
                         if (fin) {
                             if (p.out_mask & 2u)
-                                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(best[r]), mrs,
-                                                                      tid * 4, r * WG * 4, 0);
+                                stream_store_b32(__float_as_uint(best[r]), mrs,
+                                                                      tid * 4, r * WG * 4);
                             if (p.out_mask & 4u)
-                                __builtin_amdgcn_raw_buffer_store_b8(
-                                    (uint8_t)(1u << (st[r] & 255)), brs, tid, r * WG, 0);
+                                stream_store_b8(
+                                    (uint8_t)(1u << (st[r] & 255)), brs, tid, r * WG);
                             if constexpr (CAND)
                                 append_candidates(p, cands, best[r] >= p.cand_thr, d0.t.spec,
                                                   a + r * WG + tid, best[r], 1 << (st[r] & 255));
@@ -631,6 +648,9 @@ __device__ __forceinline__ float buffer_elem(__amdgpu_buffer_rsrc_t rs, int pos)
 }
 
 
+// Terms of eq. (1) whose loads a thread issues together.
+constexpr int kEq1Unroll = 4;
+
 template <int DT, int WG, int R, int CB, bool CAND>
 __global__ __launch_bounds__(WG) void k_hrms1d_eq1(const Run1DParams p)
 {
@@ -659,32 +679,65 @@ __global__ __launch_bounds__(WG) void k_hrms1d_eq1(const Run1DParams p)
             (void*)(static_cast<const char*>(p.x) + ct.xoff * Elem<DT>::kBytes), (short)0,
             N * Elem<DT>::kBytes, kBufferFlags);
 
+        // Output n = a + r WG + tid reads (n k + Lh/2) >> sh for k = 1..Lh:
+        // t below holds n0 k + Lh/2 for n0 = a + tid, and output r adds
+        // r WG k. A lane past the tile's end (at most R WG outputs further)
+        // reads past the spectrum's end, which the resource returns as zero,
+        // and its stores are discarded; n k + Lh/2 < 2^32 for every
+        // n < HRMS_MAX_BINS + R WG.
+        const unsigned n0 = (unsigned)(a + tid);
         float acc[R][kMaxLevels];
-        unsigned nn[R], tk[R];
-        bool act[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
 #pragma unroll
             for (int l = 0; l < kMaxLevels; ++l) acc[r][l] = 0.0f;
-            const int n = a + r * WG + tid;
-            act[r] = n < aend;
-            nn[r] = act[r] ? (unsigned)n : (unsigned)a;
-            tk[r] = half;   // n k + Lh/2 for k = 0
         }
-        for (int k = 1; k <= Lh; ++k) {
-            float v[R];
+        unsigned tk0 = half;
+        if (Lh >= kEq1Unroll) {
+            // kEq1Unroll terms per step, all loads issued before the first
+            // add, so that a wavefront keeps kEq1Unroll * R loads in flight
+            for (int k = 1; k <= Lh; k += kEq1Unroll) {
+                float v[kEq1Unroll][R];
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                tk[r] += nn[r];
-                // round(n k / Lh), halves up: floor((n k + Lh/2) / Lh)
-                v[r] = buffer_elem<DT>(rs, (int)(tk[r] >> sh));
+                for (int u = 0; u < kEq1Unroll; ++u) {
+                    tk0 += n0;
+                    // a uniform offset per output, kept opaque to the loop
+                    // optimiser (which would otherwise keep R kEq1Unroll running
+                    // positions in vector registers)
+                    const unsigned sk = (unsigned)__builtin_amdgcn_readfirstlane((k + u) * WG);
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        v[u][r] = buffer_elem<DT>(rs, (int)((tk0 + (unsigned)r * sk) >> sh));
+                }
+#pragma unroll
+                for (int u = 0; u < kEq1Unroll; ++u) {
+                    // k = 1 mod kEq1Unroll, so tz(k + u) = tz(u + 1) but for the last u
+                    const int tz = u + 1 < kEq1Unroll ? __builtin_ctz((unsigned)(u + 1))
+                                                      : __builtin_ctz((unsigned)(k + u));
+#pragma unroll
+                    for (int l = 0; l < kMaxLevels; ++l) {
+                        if (l >= sh - tz && l < nl) {
+#pragma unroll
+                            for (int r = 0; r < R; ++r) acc[r][l] = acc[r][l] + v[u][r];
+                        }
+                    }
+                }
             }
-            const int lmin = sh - __builtin_ctz((unsigned)k);
+        } else {
+            for (int k = 1; k <= Lh; ++k) {
+                tk0 += n0;
+                const unsigned sk = (unsigned)(k * WG);
+                const int lmin = sh - __builtin_ctz((unsigned)k);
+                float v[R];
 #pragma unroll
-            for (int l = 0; l < kMaxLevels; ++l) {
-                if (l >= lmin && l < nl) {
+                for (int r = 0; r < R; ++r)
+                    v[r] = buffer_elem<DT>(rs, (int)((tk0 + (unsigned)r * sk) >> sh));
 #pragma unroll
-                    for (int r = 0; r < R; ++r) acc[r][l] = acc[r][l] + v[r];
+                for (int l = 0; l < kMaxLevels; ++l) {
+                    if (l >= lmin && l < nl) {
+#pragma unroll
+                        for (int r = 0; r < R; ++r) acc[r][l] = acc[r][l] + v[r];
+                    }
                 }
             }
         }
@@ -709,8 +762,8 @@ __global__ __launch_bounds__(WG) void k_hrms1d_eq1(const Run1DParams p)
                 for (int r = 0; r < R; ++r) {
                     const float hv = acc[r][l] * c.rh;
                     if (p.out_mask & 1u)
-                        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(hv), hrs, tid * 4,
-                                                              r * WG * 4, 0);
+                        stream_store_b32(__float_as_uint(hv), hrs, tid * 4,
+                                                              r * WG * 4);
                     const float snr = (hv - c.m) * c.q;
                     if (l == 0 || snr > best[r]) {
                         best[r] = snr;
@@ -724,13 +777,13 @@ __global__ __launch_bounds__(WG) void k_hrms1d_eq1(const Run1DParams p)
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             if (p.out_mask & 2u)
-                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(best[r]), mrs, tid * 4,
-                                                      r * WG * 4, 0);
+                stream_store_b32(__float_as_uint(best[r]), mrs, tid * 4,
+                                                      r * WG * 4);
             if (p.out_mask & 4u)
-                __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(1u << bl[r]), brs, tid, r * WG, 0);
+                stream_store_b8((uint8_t)(1u << bl[r]), brs, tid, r * WG);
             if constexpr (CAND)
-                append_candidates(p, cands, act[r] && best[r] >= p.cand_thr, ct.spec, nn[r],
-                                  best[r], 1 << bl[r]);
+                append_candidates(p, cands, (int)n0 + r * WG < aend && best[r] >= p.cand_thr,
+                                  ct.spec, (int)n0 + r * WG, best[r], 1 << bl[r]);
         }
         __syncthreads();
         if constexpr (CAND) flush_candidates(p, cands, WG);
@@ -866,15 +919,15 @@ __global__ __launch_bounds__(WG) void k_hrms1d_gather(const Run1DParams p)
                     }
                     if (act[r]) {
                         if (p.out_mask & 1u)
-                            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(hv), hrs,
-                                                                  tid * 4, r * WG * 4, 0);
+                            stream_store_b32(__float_as_uint(hv), hrs,
+                                                                  tid * 4, r * WG * 4);
                         if (fin && track) {
                             if (p.out_mask & 2u)
-                                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(best[r]), mrs,
-                                                                      tid * 4, r * WG * 4, 0);
+                                stream_store_b32(__float_as_uint(best[r]), mrs,
+                                                                      tid * 4, r * WG * 4);
                             if (p.out_mask & 4u)
-                                __builtin_amdgcn_raw_buffer_store_b8(
-                                    (uint8_t)(1u << (st[r] & 255)), brs, tid, r * WG, 0);
+                                stream_store_b8(
+                                    (uint8_t)(1u << (st[r] & 255)), brs, tid, r * WG);
                         }
                     }
                     if (CAND && fin)
@@ -1129,8 +1182,8 @@ __device__ __forceinline__ void win_group(const Run1DParams& p, const WinTile& w
             for (int q = 0; q < NR; ++q) {
                 const float hv = S[q] * rh;
                 if (p.out_mask & 1u)
-                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(hv), hrs,
-                                                          (u0 + q * stride) * 4, 0, 0);
+                    stream_store_b32(__float_as_uint(hv), hrs,
+                                                          (u0 + q * stride) * 4, 0);
                 if (track) {
                     const float snr = (hv - m0) * q0;
                     if (li == 0 || snr > best[q]) {
@@ -1146,9 +1199,9 @@ __device__ __forceinline__ void win_group(const Run1DParams& p, const WinTile& w
         const int u = u0 + q * stride;
         if (track) {
             if (p.out_mask & 2u)
-                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(best[q]), w.mrs, u * 4, 0, 0);
+                stream_store_b32(__float_as_uint(best[q]), w.mrs, u * 4, 0);
             if (p.out_mask & 4u)
-                __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(1u << bl[q]), w.brs, u, 0, 0);
+                stream_store_b8((uint8_t)(1u << bl[q]), w.brs, u, 0);
         }
         if constexpr (CAND)
             append_candidates(p, cands, u < w.tn && best[q] >= p.cand_thr, w.spec, nn[q], best[q],
@@ -1236,7 +1289,7 @@ __device__ __forceinline__ void win_deep(const Run1DParams& p, const WinTile& w,
                         ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(w.lho_hi, li) << 32) |
                         (uint32_t)__builtin_amdgcn_readlane(w.lho_lo, li));
                     const __amdgpu_buffer_rsrc_t hrs = out_rsrc(p.h + ho + a, tn * 4);
-                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(hv), hrs, u * 4, 0, 0);
+                    stream_store_b32(__float_as_uint(hv), hrs, u * 4, 0);
                 }
                 if (track) {
                     const float m0 =
@@ -1254,9 +1307,9 @@ __device__ __forceinline__ void win_deep(const Run1DParams& p, const WinTile& w,
     }
     if (track) {
         if (p.out_mask & 2u)
-            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(best), w.mrs, u * 4, 0, 0);
+            stream_store_b32(__float_as_uint(best), w.mrs, u * 4, 0);
         if (p.out_mask & 4u)
-            __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(1u << bl), w.brs, u, 0, 0);
+            stream_store_b8((uint8_t)(1u << bl), w.brs, u, 0);
     }
     if constexpr (CAND)
         append_candidates(p, cands, act && best >= p.cand_thr, w.spec, n, best, 1 << bl);
@@ -1447,7 +1500,8 @@ __global__ __launch_bounds__(64 * kZRows) void k_hrms2d(const Run2DParams p)
             const LevelConst c = p.consts[l];
             const float hv = acc * c.rh;
             const int plane = VAR == kEq1 ? p.nf : (p.nf >> l);
-            if (p.out_mask & 1u) p.h[p.hoff[l] + (int64_t)r * plane + m] = hv;
+            if (p.out_mask & 1u)
+                __builtin_nontemporal_store(hv, p.h + p.hoff[l] + (int64_t)r * plane + m);
             const float snr = (hv - c.m) * c.q;
             if (l == 0 || snr > best) {
                 best = snr;
@@ -1456,8 +1510,8 @@ __global__ __launch_bounds__(64 * kZRows) void k_hrms2d(const Run2DParams p)
         }
     }
     const int64_t o = (int64_t)r * p.nf + m;
-    if (p.out_mask & 2u) p.max_snr[o] = best;
-    if (p.out_mask & 4u) p.best_h[o] = (uint8_t)(1u << bl);
+    if (p.out_mask & 2u) __builtin_nontemporal_store(best, p.max_snr + o);
+    if (p.out_mask & 4u) __builtin_nontemporal_store((uint8_t)(1u << bl), p.best_h + o);
 }
 
 // --------------------------------------------------------------------------
