@@ -299,6 +299,24 @@ int64_t layout_2d_into(const hrms_run2d_args* a, int64_t* plane_offsets)
 // Plans
 // ---------------------------------------------------------------------------
 
+// Half of one XCD's 4 MB L2.
+constexpr int64_t kL2HalfBytes = 2 << 20;
+
+// Outputs in flight per CU past which the gathered and window forms lose:
+// an XCD works through whole spectra, and once the input lines that its tiles
+// in flight read no longer fit its L2, more resident workgroups only add
+// re-reads through the fabric. Measured on 2^21-bin FP32 spectra at
+// Hmax = 32 (Greedy 21.7 -> 14.7 ms, freq-bin 19.5 -> 18.6, Max 23.0 -> 22.0);
+// 2-byte bins halve the lines, so twice the outputs. 0: no limit.
+int inflight_outputs_per_cu(int variant, int dtype)
+{
+    int f32 = 0;
+    if (variant == HRMS_MAX) f32 = 6144;
+    else if (variant == HRMS_FREQBIN) f32 = 8192;
+    else if (variant == HRMS_GREEDY) f32 = 4096;
+    return dtype == HRMS_F32 ? f32 : 2 * f32;
+}
+
 Shape1D default_shape(int variant, int dtype)
 {
     // measured on the 1000 x 2^21, Hmax = 32 batch
@@ -492,18 +510,30 @@ int build_plan_1d(hrms_ctx* c, const hrms_run1d_args* a, const Shape1D& shape, P
     }
     P->seg_first[ns] = (int32_t)P->segs.size();
 
-    // one resident wave of workgroups per launch, the same number per queue
+    // one resident wave of workgroups per launch, the same number per queue;
+    // on spectra that an XCD's L2 cannot hold, no more outputs in flight per
+    // CU than inflight_outputs_per_cu allows
+    int64_t big_bins = 0, all_bins = 0;
+    const int elem_bytes = a->dtype == HRMS_F32 ? 4 : 2;
+    for (const SpecDesc& sd : P->spec) {
+        all_bins += sd.n;
+        if ((int64_t)sd.n * elem_bytes >= kL2HalfBytes) big_bins += sd.n;
+    }
+    const bool l2_bound = 2 * big_bins >= all_bins;
     for (int part = 0; part < 2; ++part) {
         const std::vector<TileRec>& tiles = part ? P->tiles_top : P->tiles;
         int& grid_out = part ? P->grid_top : P->grid;
         grid_out = 0;
         if (tiles.empty()) continue;
         hipError_t oe = hipSuccess;
-        const int per_cu =
+        int per_cu =
             hrms1d_max_blocks_per_cu(a->variant, a->dtype, part ? kTopShape : shape, &oe);
         if (per_cu <= 0)
             return hip_fail(c, oe != hipSuccess ? oe : hipErrorInvalidConfiguration,
                             "occupancy query of the 1D kernel");
+        const int lim = inflight_outputs_per_cu(a->variant, a->dtype);
+        if (part == 0 && l2_bound && lim > 0)
+            per_cu = std::min(per_cu, std::max(1, lim / hrms1d_tile_outputs(a->variant, shape)));
         int64_t grid = std::min<int64_t>((int64_t)c->cu_count * per_cu, (int64_t)tiles.size());
         if (grid >= nq) grid -= grid % nq;
         grid_out = (int)std::max<int64_t>(grid, 1);
