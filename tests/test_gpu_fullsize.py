@@ -1,4 +1,4 @@
-"""GPU parity at the full size of the 1D batch: 1000 spectra of 2^21 bins,
+"""GPU parity at the full sizes: the 1D batch of 1000 spectra of 2^21 bins,
 Hmax = 32, run the way a benchmark step runs it (one statistics pass over the
 whole batch, then each of eq. (1)-(4) with those statistics provided and every
 output requested, in the default launch shapes of one persistent launch).
@@ -8,6 +8,9 @@ batch, every spectrum carrying a comb, two at random) are checked on sampled
 outputs: both ends, every level boundary, the low bins that hold all 32
 harmonics, the bins around each comb's harmonics, and a uniform sample. Only
 the sampled outputs are copied back from the device.
+
+The same sampled comparison covers one spectrum of the largest length the
+library accepts (2^26 bins).
 
 Bar: statistics within 1e-12 relative of the oracle's; SNR constants, sums,
 maximum SNR and best level bit-identical to the oracle's FP32 evaluation;
@@ -85,6 +88,37 @@ def gather(t, pos):
     return t[torch.from_numpy(pos).to(t.device)].cpu().numpy()
 
 
+def check_sampled(b, s, xs, variant, hmax, idx, g_stats, g_consts):
+    """Spectrum s of a finished batch against the oracle on the outputs idx,
+    copying only those outputs back from the device."""
+    n = xs.size
+    lo = int(b.offsets[s])
+    nl = O.num_levels(hmax)
+    mu, sd = O.stats(xs)
+    assert abs(g_stats[0] - mu) <= 1e-12 * abs(mu), (s, g_stats, mu)
+    assert abs(g_stats[1] - sd) <= 1e-12 * abs(sd), (s, g_stats, sd)
+    m32, q32, _, _ = O.snr_consts(variant, mu, sd, hmax)
+    assert np.array_equal(g_consts[:nl, 0], m32), s
+    assert np.array_equal(g_consts[:nl, 1], q32), s
+    h32, ms32, bh32, _ = O.hrms_1d(xs, variant, hmax, idx=idx, f32=True, mu=mu, sigma=sd)
+    h64, _, _, _ = O.hrms_1d(xs, variant, hmax, idx=idx, f32=False, want_snr=False)
+    for l in range(nl):
+        ln = n if variant == O.EQ1 else n >> l
+        valid = idx < ln
+        got = gather(b.h, int(b.plane_offsets[s, l]) + idx[valid]).astype(np.float64)
+        bad = np.nonzero(got != h32[l][valid])[0]
+        assert bad.size == 0, (s, l, idx[valid][bad[:5]], got[bad[:5]], h32[l][valid][bad[:5]])
+        ref = h64[l][valid]
+        rel = np.abs(got - ref) / np.maximum(np.abs(ref), 1e-30)
+        assert rel.max() <= REL_TOL_F64, (s, l, rel.max())
+    got = gather(b.max_snr, lo + idx).astype(np.float64)
+    bad = np.nonzero(got != ms32)[0]
+    assert bad.size == 0, (s, idx[bad[:5]], got[bad[:5]], ms32[bad[:5]])
+    got = gather(b.best_h, lo + idx)
+    bad = np.nonzero(got != bh32)[0]
+    assert bad.size == 0, (s, idx[bad[:5]], got[bad[:5]], bh32[bad[:5]])
+
+
 @pytest.mark.parametrize("variant", [0, 1, 2, 3])
 def test_fullsize_batch_sampled(handle, host_batch, device_batch, variant):
     import torch
@@ -96,32 +130,37 @@ def test_fullsize_batch_sampled(handle, host_batch, device_batch, variant):
     torch.cuda.synchronize()
     g_stats = stats.cpu().numpy()
     g_consts = b.consts.cpu().numpy()
-    nl = O.num_levels(HMAX)
     for s in checked_spectra(combs):
         lo, hi = int(offsets[s]), int(offsets[s + 1])
         xs = t[lo:hi].to(torch.float64).numpy()
-        mu, sd = O.stats(xs)
-        assert abs(g_stats[s, 0] - mu) <= 1e-12 * abs(mu), (s, g_stats[s], mu)
-        assert abs(g_stats[s, 1] - sd) <= 1e-12 * abs(sd), (s, g_stats[s], sd)
-        m32, q32, _, _ = O.snr_consts(variant, mu, sd, HMAX)
-        assert np.array_equal(g_consts[s, :nl, 0], m32), s
-        assert np.array_equal(g_consts[s, :nl, 1], q32), s
-        idx = sampled(s, combs)
-        h32, ms32, bh32, _ = O.hrms_1d(xs, variant, HMAX, idx=idx, f32=True, mu=mu, sigma=sd)
-        h64, _, _, _ = O.hrms_1d(xs, variant, HMAX, idx=idx, f32=False, want_snr=False)
-        for l in range(nl):
-            ln = NB if variant == O.EQ1 else NB >> l
-            valid = idx < ln
-            got = gather(b.h, int(b.plane_offsets[s, l]) + idx[valid]).astype(np.float64)
-            bad = np.nonzero(got != h32[l][valid])[0]
-            assert bad.size == 0, (s, l, idx[valid][bad[:5]], got[bad[:5]], h32[l][valid][bad[:5]])
-            ref = h64[l][valid]
-            rel = np.abs(got - ref) / np.maximum(np.abs(ref), 1e-30)
-            assert rel.max() <= REL_TOL_F64, (s, l, rel.max())
-        got = gather(b.max_snr, lo + idx).astype(np.float64)
-        bad = np.nonzero(got != ms32)[0]
-        assert bad.size == 0, (s, idx[bad[:5]], got[bad[:5]], ms32[bad[:5]])
-        got = gather(b.best_h, lo + idx)
-        bad = np.nonzero(got != bh32)[0]
-        assert bad.size == 0, (s, idx[bad[:5]], got[bad[:5]], bh32[bad[:5]])
+        check_sampled(b, s, xs, variant, HMAX, sampled(s, combs), g_stats[s], g_consts[s])
     del b
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+def test_maximum_length_spectrum_sampled(handle, variant):
+    """One spectrum of the largest length the library accepts (2^26 bins),
+    Hmax = 32, after a shorter one, so that the largest positions, offsets
+    and running products of the kernels are reached; sampled outputs,
+    including the last bins of every level."""
+    import torch
+    from paper_1812_02647_amd import hrms as H
+    N = H.HRMS_MAX_BINS
+    x, offsets, combs = synth.batch(2, [1000, N], seed=37, comb_fraction=1.0)
+    xd = torch.from_numpy(x).to("cuda")
+    case_log(f"maximum length variant={NAMES[variant]} N={N} Hmax={HMAX}")
+    b = H.Batch1D(xd, offsets, variant, HMAX, out_mask=H.HRMS_OUT_ALL).run(handle)
+    torch.cuda.synchronize()
+    g_stats = b.stats.cpu().numpy()
+    g_consts = b.consts.cpu().numpy()
+    idx = sample_indices(N, HMAX, 3000, np.random.default_rng(variant))
+    f0 = [f for sp, f in combs if sp == 1][0]
+    extra = [j for k in range(1, HMAX + 1) for j in range(int(k * f0) - 2, int(k * f0) + 3)]
+    idx = np.unique(np.concatenate([idx, np.array(extra, np.int64)]))
+    idx = idx[(idx >= 0) & (idx < N)]
+    check_sampled(b, 1, x[int(offsets[1]):].astype(np.float64), variant, HMAX, idx,
+                  g_stats[1], g_consts[1])
+    check_sampled(b, 0, x[:int(offsets[1])].astype(np.float64), variant, HMAX,
+                  np.arange(1000, dtype=np.int64), g_stats[0], g_consts[0])
+    del b, xd
+    torch.cuda.empty_cache()

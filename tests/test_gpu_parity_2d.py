@@ -27,6 +27,12 @@ def handle():
 
 
 def run_2d(handle, plane_dev, nf, zmax, hmax, variant, ld=None, stats=None, out_mask=7):
+    out = run_2d_device(handle, plane_dev, nf, zmax, hmax, variant, ld, stats, out_mask)
+    return {k: (v.cpu().numpy() if k != "offs" else v) for k, v in out.items()}
+
+
+def run_2d_device(handle, plane_dev, nf, zmax, hmax, variant, ld=None, stats=None, out_mask=7):
+    """One plane through the C ABI; the outputs stay on the device."""
     import torch
     from paper_1812_02647_amd import hrms as H
     a = H.hrms_run2d_args()
@@ -49,8 +55,7 @@ def run_2d(handle, plane_dev, nf, zmax, hmax, variant, ld=None, stats=None, out_
     a.h, a.max_snr, a.best_h = h.data_ptr(), ms.data_ptr(), bh.data_ptr()
     H.hrms_run_2d(handle, a)
     torch.cuda.synchronize()
-    return {"offs": offs, "h": h.cpu().numpy(), "max_snr": ms.cpu().numpy(),
-            "best_h": bh.cpu().numpy(), "stats": st.cpu().numpy(), "consts": consts.cpu().numpy()}
+    return {"offs": offs, "h": h, "max_snr": ms, "best_h": bh, "stats": st, "consts": consts}
 
 
 def check_plane(out, seen, nf, zmax, hmax, variant, fidx=None, zidx=None, stats=None,
@@ -167,3 +172,46 @@ def test_variants_alternate_on_one_handle(handle):
         case_log(f"2d alternating variants: {NAMES[variant]}")
         out = run_2d(handle, xd, nf, zmax, 8, variant)
         check_plane(out, seen, nf, zmax, 8, variant, label=f"alt-{NAMES[variant]}")
+
+
+@pytest.mark.parametrize("variant", [O.EQ1, O.MAX, O.FREQBIN, O.GREEDY])
+def test_maximum_length_rows_sampled(handle, variant):
+    """Rows of the largest length the library accepts (2^26 frequency bins),
+    3 fdot rows, Hmax = 16; sampled outputs, including the last bins of every
+    level, copied back alone."""
+    import torch
+    from paper_1812_02647_amd import hrms as H
+    zmax, nf = 1, H.HRMS_MAX_BINS
+    x, _ = synth.plane(nf=nf, zmax=zmax, seed=57, n_comb=4, z0_max=0)
+    xd = torch.from_numpy(x).to("cuda")
+    case_log(f"2d maximum length variant={NAMES[variant]} 3x2^26")
+    out = run_2d_device(handle, xd, nf, zmax, 16, variant)
+    rng = np.random.default_rng(variant)
+    fidx = [np.arange(0, 40), np.arange(nf - 40, nf)]
+    for H_ in (2, 4, 8, 16):
+        fidx.append(nf // H_ + np.arange(-3, 3))
+    fidx += [rng.integers(0, nf // 16, 1000), rng.integers(0, nf, 1000)]
+    fidx = np.concatenate(fidx).astype(np.int64)
+    zidx = rng.integers(-zmax, zmax + 1, fidx.size).astype(np.int32)
+    seen = x.astype(np.float64)
+    mu, sd = O.stats(seen)
+    st = out["stats"].cpu().numpy()
+    assert abs(st[0] - mu) <= 1e-12 * abs(mu) and abs(st[1] - sd) <= 1e-12 * abs(sd)
+    h32, ms32, bh32, _ = O.hrms_2d(seen, zmax, variant, 16, fidx=fidx, zidx=zidx, f32=True,
+                                    mu=mu, sigma=sd)
+    r = zidx.astype(np.int64) + zmax
+
+    def gather(t, pos):
+        return t[torch.from_numpy(pos).to(t.device)].cpu().numpy()
+
+    for l in range(O.num_levels(16)):
+        ln = nf if variant == O.EQ1 else nf >> l
+        valid = fidx < ln
+        got = gather(out["h"], out["offs"][l] + r[valid] * ln + fidx[valid]).astype(np.float64)
+        bad = np.nonzero(got != h32[l][valid])[0]
+        assert bad.size == 0, (l, fidx[valid][bad[:5]], got[bad[:5]], h32[l][valid][bad[:5]])
+    o = r * nf + fidx
+    assert np.array_equal(gather(out["max_snr"], o).astype(np.float64), ms32)
+    assert np.array_equal(gather(out["best_h"], o), bh32)
+    del out, xd
+    torch.cuda.empty_cache()
