@@ -590,8 +590,7 @@ __global__ __launch_bounds__(WG) void k_hrms1d_span(const Run1DParams p)
                     acc[r] = acc[r] + tv;
                     const float hv = acc[r] * rh;
                     if (p.out_mask & 1u)
-                        stream_store_b32(__float_as_uint(hv), hrs, tid * 4,
-                                                              r * WG * 4);
+                        stream_store_b32(__float_as_uint(hv), hrs, tid * 4, r * WG * 4);
                     if (track) {
                         const float snr = (hv - m0) * q0;
                         if (li == 0 || snr > best[r]) {
@@ -600,11 +599,10 @@ __global__ __launch_bounds__(WG) void k_hrms1d_span(const Run1DParams p)
                         }
                         if (fin) {
                             if (p.out_mask & 2u)
-                                stream_store_b32(__float_as_uint(best[r]), mrs,
-                                                                      tid * 4, r * WG * 4);
+                                stream_store_b32(__float_as_uint(best[r]), mrs, tid * 4,
+                                                 r * WG * 4);
                             if (p.out_mask & 4u)
-                                stream_store_b8(
-                                    (uint8_t)(1u << (st[r] & 255)), brs, tid, r * WG);
+                                stream_store_b8((uint8_t)(1u << (st[r] & 255)), brs, tid, r * WG);
                             if constexpr (CAND)
                                 append_candidates(p, cands, best[r] >= p.cand_thr, d0.t.spec,
                                                   a + r * WG + tid, best[r], 1 << (st[r] & 255));
@@ -762,8 +760,7 @@ __global__ __launch_bounds__(WG) void k_hrms1d_eq1(const Run1DParams p)
                 for (int r = 0; r < R; ++r) {
                     const float hv = acc[r][l] * c.rh;
                     if (p.out_mask & 1u)
-                        stream_store_b32(__float_as_uint(hv), hrs, tid * 4,
-                                                              r * WG * 4);
+                        stream_store_b32(__float_as_uint(hv), hrs, tid * 4, r * WG * 4);
                     const float snr = (hv - c.m) * c.q;
                     if (l == 0 || snr > best[r]) {
                         best[r] = snr;
@@ -777,8 +774,7 @@ __global__ __launch_bounds__(WG) void k_hrms1d_eq1(const Run1DParams p)
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             if (p.out_mask & 2u)
-                stream_store_b32(__float_as_uint(best[r]), mrs, tid * 4,
-                                                      r * WG * 4);
+                stream_store_b32(__float_as_uint(best[r]), mrs, tid * 4, r * WG * 4);
             if (p.out_mask & 4u)
                 stream_store_b8((uint8_t)(1u << bl[r]), brs, tid, r * WG);
             if constexpr (CAND)
@@ -919,15 +915,13 @@ __global__ __launch_bounds__(WG) void k_hrms1d_gather(const Run1DParams p)
                     }
                     if (act[r]) {
                         if (p.out_mask & 1u)
-                            stream_store_b32(__float_as_uint(hv), hrs,
-                                                                  tid * 4, r * WG * 4);
+                            stream_store_b32(__float_as_uint(hv), hrs, tid * 4, r * WG * 4);
                         if (fin && track) {
                             if (p.out_mask & 2u)
-                                stream_store_b32(__float_as_uint(best[r]), mrs,
-                                                                      tid * 4, r * WG * 4);
+                                stream_store_b32(__float_as_uint(best[r]), mrs, tid * 4,
+                                                 r * WG * 4);
                             if (p.out_mask & 4u)
-                                stream_store_b8(
-                                    (uint8_t)(1u << (st[r] & 255)), brs, tid, r * WG);
+                                stream_store_b8((uint8_t)(1u << (st[r] & 255)), brs, tid, r * WG);
                         }
                     }
                     if (CAND && fin)
@@ -1182,8 +1176,7 @@ __device__ __forceinline__ void win_group(const Run1DParams& p, const WinTile& w
             for (int q = 0; q < NR; ++q) {
                 const float hv = S[q] * rh;
                 if (p.out_mask & 1u)
-                    stream_store_b32(__float_as_uint(hv), hrs,
-                                                          (u0 + q * stride) * 4, 0);
+                    stream_store_b32(__float_as_uint(hv), hrs, (u0 + q * stride) * 4, 0);
                 if (track) {
                     const float snr = (hv - m0) * q0;
                     if (li == 0 || snr > best[q]) {
