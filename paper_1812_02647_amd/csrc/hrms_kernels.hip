@@ -1213,7 +1213,13 @@ constexpr int kWinWaveWords = 64 * 32 + 64;
 // of k bins from there. Only the wave touches its area, and its LDS accesses
 // are carried out in order, so no barrier is needed. Lanes past the tile's end
 // work on the tile's first output and discard the result.
-template <int VAR, int DT, bool CAND>
+//
+// For eq. (2) on FP32 bins the loads of harmonic k + 1 are issued before
+// harmonic k is staged and reduced, so that a wave always has the next
+// harmonic's bins in flight (HT, the band's top level, 16 or 32, is then a
+// template argument so that whether a next harmonic exists is known at
+// compile time).
+template <int VAR, int DT, int HT, bool CAND>
 __device__ __forceinline__ void win_deep(const Run1DParams& p, const WinTile& w,
                                          const __amdgpu_buffer_rsrc_t rs, const int a, const int tn,
                                          const int ht, int u, bool track, CandStage& cands,
@@ -1229,71 +1235,86 @@ __device__ __forceinline__ void win_deep(const Run1DParams& p, const WinTile& w,
     int bl = 0;
     float P[VAR == kOpt ? 32 : 1];
     float acc = 0.0f;
+    // (2-byte bins: the extra registers cost a resident wave, and it loses)
+    constexpr bool kAhead = VAR == kMax && DT == kF32;
+    float vn[kAhead ? 32 : 1];   // bins of the next harmonic, in flight
+    if constexpr (kAhead) vn[0] = buffer_elem<DT>(rs, n0 + lane);
 #pragma unroll
-    for (int k = 1; k <= 32; ++k) {
-        if (k <= ht) {
-            {
-                float v[32];
+    for (int k = 1; k <= HT; ++k) {
+        // without the look-ahead the band's top level stays a run-time bound
+        // (HT = 32), which keeps the other forms' registers as they were
+        if (!kAhead && k > ht) continue;
+        {
+            float v[32];
+            if constexpr (kAhead) {
+#pragma unroll
+                for (int t = 0; t < k; ++t) v[t] = vn[t];
+                if (k < HT) {
+                    const int rnext = (k + 1) * n0 + lane;
+#pragma unroll
+                    for (int t = 0; t <= k; ++t) vn[t] = buffer_elem<DT>(rs, rnext + 64 * t);
+                }
+            } else {
                 const int rbase = k * n0 + lane;
 #pragma unroll
                 for (int t = 0; t < k; ++t) v[t] = buffer_elem<DT>(rs, rbase + 64 * t);
-                __builtin_amdgcn_wave_barrier();   // the previous windows are read
-#pragma unroll
-                for (int t = 0; t < k; ++t) wl[pidx(lane + 64 * t)] = v[t];
-                __builtin_amdgcn_wave_barrier();
             }
-            float xv[32];
-            const int wb = act ? k * lane : 0;
+            __builtin_amdgcn_wave_barrier();   // the previous windows are read
 #pragma unroll
-            for (int j = 0; j < k; ++j) xv[j] = wl[pidx(wb + j)];
-            float S = 0.0f;
-            if constexpr (VAR == kMax) {
-                float tv = xv[0];
+            for (int t = 0; t < k; ++t) wl[pidx(lane + 64 * t)] = v[t];
+            __builtin_amdgcn_wave_barrier();
+        }
+        float xv[32];
+        const int wb = act ? k * lane : 0;
 #pragma unroll
-                for (int j = 1; j < k; ++j) tv = xv[j] > tv ? xv[j] : tv;
-                acc = acc + tv;
-                S = acc;
+        for (int j = 0; j < k; ++j) xv[j] = wl[pidx(wb + j)];
+        float S = 0.0f;
+        if constexpr (VAR == kMax) {
+            float tv = xv[0];
+#pragma unroll
+            for (int j = 1; j < k; ++j) tv = xv[j] > tv ? xv[j] : tv;
+            acc = acc + tv;
+            S = acc;
+        } else {
+            if (k == 1) {
+                P[0] = xv[0];
             } else {
-                if (k == 1) {
-                    P[0] = xv[0];
-                } else {
-                    // top down, so that every update reads the previous states
-                    P[k - 1] = P[k - 2] + xv[k - 1];
+                // top down, so that every update reads the previous states
+                P[k - 1] = P[k - 2] + xv[k - 1];
 #pragma unroll
-                    for (int j = k - 2; j >= 1; --j) {
-                        const float m = P[j - 1] > P[j] ? P[j - 1] : P[j];
-                        P[j] = m + xv[j];
-                    }
-                    P[0] = P[0] + xv[0];
+                for (int j = k - 2; j >= 1; --j) {
+                    const float m = P[j - 1] > P[j] ? P[j - 1] : P[j];
+                    P[j] = m + xv[j];
                 }
-                if ((k & (k - 1)) == 0) {
-                    S = P[0];
-#pragma unroll
-                    for (int j = 1; j < k; ++j) S = P[j] > S ? P[j] : S;
-                }
+                P[0] = P[0] + xv[0];
             }
             if ((k & (k - 1)) == 0) {
-                const int li = __builtin_ctz((unsigned)k);
-                const float rh =
-                    __int_as_float(__builtin_amdgcn_readlane(__float_as_int(w.lrh), li));
-                const float hv = S * rh;
-                if (p.out_mask & 1u) {
-                    const int64_t ho = (int64_t)(
-                        ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(w.lho_hi, li) << 32) |
-                        (uint32_t)__builtin_amdgcn_readlane(w.lho_lo, li));
-                    const __amdgpu_buffer_rsrc_t hrs = out_rsrc(p.h + ho + a, tn * 4);
-                    stream_store_b32(__float_as_uint(hv), hrs, u * 4, 0);
-                }
-                if (track) {
-                    const float m0 =
-                        __int_as_float(__builtin_amdgcn_readlane(__float_as_int(w.lm), li));
-                    const float q0 =
-                        __int_as_float(__builtin_amdgcn_readlane(__float_as_int(w.lq), li));
-                    const float snr = (hv - m0) * q0;
-                    if (li == 0 || snr > best) {
-                        best = snr;
-                        bl = li;
-                    }
+                S = P[0];
+#pragma unroll
+                for (int j = 1; j < k; ++j) S = P[j] > S ? P[j] : S;
+            }
+        }
+        if ((k & (k - 1)) == 0) {
+            const int li = __builtin_ctz((unsigned)k);
+            const float rh =
+                __int_as_float(__builtin_amdgcn_readlane(__float_as_int(w.lrh), li));
+            const float hv = S * rh;
+            if (p.out_mask & 1u) {
+                const int64_t ho = (int64_t)(
+                    ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(w.lho_hi, li) << 32) |
+                    (uint32_t)__builtin_amdgcn_readlane(w.lho_lo, li));
+                const __amdgpu_buffer_rsrc_t hrs = out_rsrc(p.h + ho + a, tn * 4);
+                stream_store_b32(__float_as_uint(hv), hrs, u * 4, 0);
+            }
+            if (track) {
+                const float m0 =
+                    __int_as_float(__builtin_amdgcn_readlane(__float_as_int(w.lm), li));
+                const float q0 =
+                    __int_as_float(__builtin_amdgcn_readlane(__float_as_int(w.lq), li));
+                const float snr = (hv - m0) * q0;
+                if (li == 0 || snr > best) {
+                    best = snr;
+                    bl = li;
                 }
             }
         }
@@ -1367,10 +1388,16 @@ __global__ __launch_bounds__(WG) void k_hrms1d_win(const Run1DParams p)
 #pragma unroll 1
             for (int u0 = 0; u0 < w.tn; u0 += 2 * WG)
                 win_group<VAR, DT, 8, 2, CAND>(p, w, u0 + tid, WG, track, cands);
+        } else if (VAR == kMax && DT == kF32 && w.ht == 16) {
+#pragma unroll 1
+            for (int u0 = 0; u0 < w.tn; u0 += WG)
+                win_deep<VAR, DT, 16, CAND>(p, w, w.rs, w.a, w.tn, w.ht, u0 + tid, track, cands,
+                                            wl);
         } else {
 #pragma unroll 1
             for (int u0 = 0; u0 < w.tn; u0 += WG)
-                win_deep<VAR, DT, CAND>(p, w, w.rs, w.a, w.tn, w.ht, u0 + tid, track, cands, wl);
+                win_deep<VAR, DT, 32, CAND>(p, w, w.rs, w.a, w.tn, w.ht, u0 + tid, track, cands,
+                                            wl);
         }
         __syncthreads();
         if constexpr (CAND) flush_candidates(p, cands, WG);
