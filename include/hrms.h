@@ -22,8 +22,9 @@
  * Fourier-domain acceleration search; abstract, Sec. 1).
  *
  * Conventions shared by every entry point
- *   - Levels are H = 1, 2, 4, ..., hmax with hmax a power of two <= 32
- *     ("partial sums of an increasing number of harmonics", Sec. 1).
+ *   - Levels are H = 1, 2, 4, ..., hmax with hmax a power of two <= 32: the
+ *     sum is reported after every doubling of the number of harmonics added
+ *     (Sec. 1).
  *   - round() in eq. (1) rounds halves up; the fdot row of the 2D sum rounds
  *     halves away from zero. All index arithmetic is exact integer arithmetic.
  *   - Level H of output n exists for every n with eq. (1), and for
@@ -50,7 +51,12 @@
  *     caller memory. "host" arrays are read during the call only.
  *   - Work is enqueued asynchronously on the given HIP stream (NULL = the null
  *     stream). Buffers must stay alive until the stream reaches the work.
- *   - A handle is not thread-safe; use one handle per host thread.
+ *   - A handle is not thread-safe; use one handle per host thread. Calls on one
+ *     handle may use different streams: a call that reuses the device scratch
+ *     of an earlier call with the same batch signature (1D: offsets, Hmax,
+ *     variant, storage type and launch shape; 2D: the plane's shape; the
+ *     precision form: offsets) waits on its stream for that call's work to
+ *     finish, so such calls run one after the other; other calls may overlap.
  *   - Every argument is checked before anything is enqueued. On error nothing
  *     is enqueued, no output is touched and a negative status is returned;
  *     hrms_last_error() gives the reason. No call aborts or throws.
@@ -183,7 +189,13 @@ typedef struct {
 
 /* Normalisation to unit mean and narrow storage (FP16 / BF16) of FP32 spectra:
  * y = round_to_dtype(x * fl32(1/mu)), rounding to nearest even, FP16 saturating
- * at +-65504. The statistics of y are taken as mu' = 1, sigma' = sigma / mu. */
+ * at +-65504. The statistics of y are taken as mu' = 1, sigma' = sigma / mu.
+ * With HRMS_STATS_PROVIDED the call reads stats back once the work already
+ * queued on the stream is done (it blocks until then) and returns
+ * HRMS_E_INVAL, enqueuing nothing, unless every mu is a positive finite number
+ * and every sigma a non-negative finite one. With HRMS_STATS_COMPUTE a
+ * spectrum whose computed mean is not positive (an all-zero spectrum) is
+ * stored unscaled and stats_out receives its own (mu, sigma). */
 typedef struct {
     int32_t n_spectra;
     int32_t dtype;            /* HRMS_F16 or HRMS_BF16 */

@@ -58,6 +58,64 @@ struct DeviceBuf {
     }
 };
 
+// Calls on one handle that reuse a plan share its device scratch (queue
+// counters, statistics partials, constants). A plan therefore remembers the
+// stream of its last use and an event recorded after that work; a later call
+// on another stream waits for the event first, and a plan is freed only once
+// its event has completed.
+struct UseOrder {
+    hipEvent_t done = nullptr;
+    hipStream_t last = nullptr;
+    bool used = false;
+    ~UseOrder()
+    {
+        if (done) {
+            if (used) (void)hipEventSynchronize(done);
+            (void)hipEventDestroy(done);
+        }
+    }
+    // Orders the coming work on `s` after the previous use.
+    hipError_t before(hipStream_t s)
+    {
+        if (!done) {
+            hipError_t e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
+            if (e != hipSuccess) {
+                done = nullptr;
+                return e;
+            }
+        }
+        if (used && s != last) return hipStreamWaitEvent(s, done, 0);
+        return hipSuccess;
+    }
+    // Marks the work just enqueued on `s` as the plan's latest use.
+    hipError_t after(hipStream_t s)
+    {
+        hipError_t e = hipEventRecord(done, s);
+        if (e != hipSuccess) return e;
+        last = s;
+        used = true;
+        return hipSuccess;
+    }
+};
+
+// Records a plan's use on every exit of a launch sequence, including an exit
+// after a failed launch that follows launches already enqueued.
+struct UseGuard {
+    UseOrder& o;
+    hipStream_t s;
+    bool armed = true;
+    UseGuard(UseOrder& o_, hipStream_t s_) : o(o_), s(s_) {}
+    hipError_t finish()
+    {
+        armed = false;
+        return o.after(s);
+    }
+    ~UseGuard()
+    {
+        if (armed) (void)o.after(s);
+    }
+};
+
 struct Plan1D {
     // signature
     std::vector<int64_t> offsets;
@@ -79,8 +137,10 @@ struct Plan1D {
     // instantiated launch sequence for the most recent argument pointers
     hipGraphExec_t gexec = nullptr;
     std::vector<const void*> gkey;
+    UseOrder order;   // declared last: destroyed first, after waiting for the last use
     ~Plan1D()
     {
+        if (order.used) (void)hipEventSynchronize(order.done);
         if (gexec) (void)hipGraphExecDestroy(gexec);
     }
 };
@@ -94,6 +154,7 @@ struct Plan2D {
     std::vector<int32_t> seg_first;   // {0, nsegs}
     std::vector<SpecDesc> plane;      // one descriptor: n = rows * nf
     DeviceBuf d_rows, d_segs, d_seg_first, d_plane, d_partial, d_consts;
+    UseOrder order;
 };
 
 // Precision form of a batch: statistics segments and fl32(1 / mu) per spectrum.
@@ -103,6 +164,7 @@ struct PlanQ {
     std::vector<Seg> segs;
     std::vector<int32_t> seg_first;
     DeviceBuf d_spec, d_segs, d_seg_first, d_partial, d_inv;
+    UseOrder order;
 };
 
 // Tuned launch shape of a class of 1D batches.
@@ -336,8 +398,9 @@ hipError_t upload(DeviceBuf& b, const std::vector<T>& v, hipStream_t s)
     return hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
 }
 
-int build_plan_1d(hrms_ctx* c, const hrms_run1d_args* a, const Shape1D& shape, Plan1D* P,
-                  hipStream_t stream)
+// Host part of a 1D plan: descriptors, tile queues, statistics segments and
+// grid sizes. Touches no device memory.
+int plan_host_1d(hrms_ctx* c, const hrms_run1d_args* a, const Shape1D& shape, Plan1D* P)
 {
     const int ns = a->n_spectra;
     P->offsets.assign(a->offsets, a->offsets + ns + 1);
@@ -539,6 +602,13 @@ int build_plan_1d(hrms_ctx* c, const hrms_run1d_args* a, const Shape1D& shape, P
         grid_out = (int)std::max<int64_t>(grid, 1);
     }
 
+    return HRMS_OK;
+}
+
+// Device copies of a plan in buffers the plan owns (allocated on first use).
+int upload_plan_1d(hrms_ctx* c, Plan1D* P, hipStream_t stream)
+{
+    const int ns = (int)P->spec.size();
     hipError_t e;
     if ((e = upload(P->d_spec, P->spec, stream)) != hipSuccess) return hip_fail(c, e, "upload spec");
     if ((e = upload(P->d_tiles, P->tiles, stream)) != hipSuccess)
@@ -585,7 +655,7 @@ int get_plan_2d(hrms_ctx* c, const hrms_run2d_args* a, hipStream_t stream, Plan2
         *out = P;
         return HRMS_OK;
     }
-    if (P) (void)hipStreamSynchronize(stream);
+    // (the old plan waits for its last use before its buffers are freed)
     c->plan2d.reset(new (std::nothrow) Plan2D());
     P = c->plan2d.get();
     if (!P) return fail(c, HRMS_E_NOMEM, "host allocation failed");
@@ -631,7 +701,6 @@ int get_plan_q(hrms_ctx* c, const hrms_quantize_args* a, hipStream_t stream, Pla
         *out = P;
         return HRMS_OK;
     }
-    if (P) (void)hipStreamSynchronize(stream);
     c->planq.reset(new (std::nothrow) PlanQ());
     P = c->planq.get();
     if (!P) return fail(c, HRMS_E_NOMEM, "host allocation failed");
@@ -680,6 +749,28 @@ int validate_q(hrms_ctx* c, const hrms_quantize_args* a)
     return HRMS_OK;
 }
 
+// Provided statistics of the precision form are read back (after the work
+// already queued on the stream) and must give a positive finite mean and a
+// non-negative finite sigma: 1 / mu scales every bin.
+int check_provided_q(hrms_ctx* c, const hrms_quantize_args* a, hipStream_t stream)
+{
+    std::vector<double> st((size_t)a->n_spectra * 2);
+    hipError_t e = hipMemcpyAsync(st.data(), a->stats, st.size() * sizeof(double),
+                                  hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(c, e, "reading the provided statistics");
+    for (int s = 0; s < a->n_spectra; ++s) {
+        const double mu = st[2 * (size_t)s], sd = st[2 * (size_t)s + 1];
+        if (!(std::isfinite(mu) && mu > 0.0))
+            return fail(c, HRMS_E_INVAL, "provided mean of spectrum " + std::to_string(s) +
+                                             " is not a positive finite number");
+        if (!(std::isfinite(sd) && sd >= 0.0))
+            return fail(c, HRMS_E_INVAL, "provided sigma of spectrum " + std::to_string(s) +
+                                             " is not a non-negative finite number");
+    }
+    return HRMS_OK;
+}
+
 bool same_signature(const Plan1D& P, const hrms_run1d_args* a, const Shape1D& shape)
 {
     if (P.variant != a->variant || P.dtype != a->dtype) return false;
@@ -708,11 +799,11 @@ int get_plan_1d(hrms_ctx* c, const hrms_run1d_args* a, const Shape1D& shape, hip
     }
     std::unique_ptr<Plan1D> p(new (std::nothrow) Plan1D());
     if (!p) return fail(c, HRMS_E_NOMEM, "host allocation failed");
-    int st = build_plan_1d(c, a, shape, p.get(), stream);
+    int st = plan_host_1d(c, a, shape, p.get());
+    if (st == HRMS_OK) st = upload_plan_1d(c, p.get(), stream);
     if (st != HRMS_OK) return st;
     if ((int)c->plans.size() >= kPlanCache) {
-        // plans still referenced by queued work must outlive it
-        (void)hipStreamSynchronize(stream);
+        // the evicted plan waits for its last use before its buffers are freed
         c->plans.erase(c->plans.begin());
     }
     c->plans.push_back(std::move(p));
@@ -788,25 +879,49 @@ void save_tune(hrms_ctx* c)
     if (ok) std::rename(tmp.c_str(), c->tune_path.c_str());
 }
 
+// Device addresses of a plan's tables and scratch: the plan's own buffers, or
+// sections of the static scratch of the entry point that allocates nothing.
+struct PlanDev {
+    const SpecDesc* spec;
+    const TileRec* tiles;
+    const int32_t* qbeg;
+    const TileRec* tiles_top;
+    const int32_t* qbeg_top;
+    const Seg* segs;
+    const int32_t* seg_first;
+    double* partial;
+    LevelConst* consts;
+    unsigned int* counters;
+};
+
+PlanDev plan_dev(const Plan1D& P)
+{
+    return PlanDev{(const SpecDesc*)P.d_spec.p,      (const TileRec*)P.d_tiles.p,
+                   (const int32_t*)P.d_qbeg.p,       (const TileRec*)P.d_tiles_top.p,
+                   (const int32_t*)P.d_qbeg_top.p,   (const Seg*)P.d_segs.p,
+                   (const int32_t*)P.d_seg_first.p,  (double*)P.d_partial.p,
+                   (LevelConst*)P.d_consts.p,        (unsigned int*)P.d_counter.p};
+}
+
 // Enqueues statistics (or not), constants and the harmonic sum.
-hipError_t enqueue_1d(const hrms_run1d_args* a, Plan1D* P, const Shape1D& shape, hipStream_t stream)
+hipError_t enqueue_1d(const hrms_run1d_args* a, const Plan1D* P, const PlanDev& D,
+                      const Shape1D& shape, hipStream_t stream)
 {
     hipError_t e;
     const bool compute = a->stats_mode == HRMS_STATS_COMPUTE;
     if (compute) {
-        StatsParams sp{a->x, (const SpecDesc*)P->d_spec.p, (const Seg*)P->d_segs.p,
-                       (double*)P->d_partial.p, (int32_t)P->segs.size()};
+        StatsParams sp{a->x, D.spec, D.segs, D.partial, (int32_t)P->segs.size()};
         if ((e = launch_stats_partial(a->dtype, sp, stream)) != hipSuccess) return e;
     }
     ConstsParams cp{};
-    cp.spec = (const SpecDesc*)P->d_spec.p;
-    cp.segs = (const Seg*)P->d_segs.p;
-    cp.seg_first = (const int32_t*)P->d_seg_first.p;
-    cp.partial = (const double*)P->d_partial.p;
+    cp.spec = D.spec;
+    cp.segs = D.segs;
+    cp.seg_first = D.seg_first;
+    cp.partial = D.partial;
     cp.stats = a->stats;
-    cp.consts = (LevelConst*)P->d_consts.p;
+    cp.consts = D.consts;
     cp.user_consts = a->snr_consts;
-    cp.counters = (unsigned int*)P->d_counter.p;
+    cp.counters = D.counters;
     cp.cand_count = (a->out_mask & (HRMS_OUT_CAND | HRMS_OUT_PEAKS)) ? a->cand_count : nullptr;
     cp.n_spec = a->n_spectra;
     cp.variant = a->variant;
@@ -815,14 +930,14 @@ hipError_t enqueue_1d(const hrms_run1d_args* a, Plan1D* P, const Shape1D& shape,
     if (a->out_mask != 0) {
         Run1DParams rp{};
         rp.x = a->x;
-        rp.spec = (const SpecDesc*)P->d_spec.p;
-        rp.tiles = (const TileRec*)P->d_tiles.p;
-        rp.consts = (const LevelConst*)P->d_consts.p;
+        rp.spec = D.spec;
+        rp.tiles = D.tiles;
+        rp.consts = D.consts;
         rp.h = a->h;
         rp.max_snr = a->max_snr;
         rp.best_h = a->best_h;
-        rp.qbeg = (const int32_t*)P->d_qbeg.p;
-        rp.counters = (unsigned int*)P->d_counter.p;
+        rp.qbeg = D.qbeg;
+        rp.counters = D.counters;
         rp.nqueues = P->nqueues;
         rp.out_mask = a->out_mask;
         rp.cand = reinterpret_cast<CandRec*>(a->cand);
@@ -833,9 +948,9 @@ hipError_t enqueue_1d(const hrms_run1d_args* a, Plan1D* P, const Shape1D& shape,
             (e = launch_hrms1d(a->variant, a->dtype, shape, rp, P->grid, stream)) != hipSuccess)
             return e;
         if (!P->tiles_top.empty()) {
-            rp.tiles = (const TileRec*)P->d_tiles_top.p;
-            rp.qbeg = (const int32_t*)P->d_qbeg_top.p;
-            rp.counters = (unsigned int*)P->d_counter.p + kMaxQueues;
+            rp.tiles = D.tiles_top;
+            rp.qbeg = D.qbeg_top;
+            rp.counters = D.counters + kMaxQueues;
             if ((e = launch_hrms1d(a->variant, a->dtype, kTopShape, rp, P->grid_top, stream)) !=
                 hipSuccess)
                 return e;
@@ -845,8 +960,8 @@ hipError_t enqueue_1d(const hrms_run1d_args* a, Plan1D* P, const Shape1D& shape,
         PeakParams pp{};
         pp.max_snr = a->max_snr;
         pp.best_h = (a->out_mask & HRMS_OUT_BESTH) ? a->best_h : nullptr;
-        pp.spec = (const SpecDesc*)P->d_spec.p;
-        pp.segs = (const Seg*)P->d_segs.p;
+        pp.spec = D.spec;
+        pp.segs = D.segs;
         pp.cand = reinterpret_cast<CandRec*>(a->cand);
         pp.cand_count = a->cand_count;
         pp.cand_cap = a->cand_capacity;
@@ -866,8 +981,12 @@ int run_1d_with(hrms_ctx* h, const hrms_run1d_args* a, hipStream_t stream, const
     int st = get_plan_1d(h, a, shape, stream, &P);
     if (st != HRMS_OK) return st;
     hipError_t e;
+    if ((e = P->order.before(stream)) != hipSuccess) return hip_fail(h, e, "stream ordering");
     if (!graphs) {
-        if ((e = enqueue_1d(a, P, shape, stream)) != hipSuccess) return hip_fail(h, e, "launch");
+        UseGuard use(P->order, stream);
+        if ((e = enqueue_1d(a, P, plan_dev(*P), shape, stream)) != hipSuccess)
+            return hip_fail(h, e, "launch");
+        if ((e = use.finish()) != hipSuccess) return hip_fail(h, e, "hipEventRecord");
         return HRMS_OK;
     }
     uint32_t thr_bits;
@@ -887,7 +1006,7 @@ int run_1d_with(hrms_ctx* h, const hrms_run1d_args* a, hipStream_t stream, const
         }
         if ((e = hipStreamBeginCapture(h->capture, hipStreamCaptureModeThreadLocal)) != hipSuccess)
             return hip_fail(h, e, "hipStreamBeginCapture");
-        const hipError_t le = enqueue_1d(a, P, shape, h->capture);
+        const hipError_t le = enqueue_1d(a, P, plan_dev(*P), shape, h->capture);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(h->capture, &g);
         if (le != hipSuccess || e != hipSuccess) {
@@ -903,6 +1022,7 @@ int run_1d_with(hrms_ctx* h, const hrms_run1d_args* a, hipStream_t stream, const
         P->gkey = key;
     }
     if ((e = hipGraphLaunch(P->gexec, stream)) != hipSuccess) return hip_fail(h, e, "hipGraphLaunch");
+    if ((e = P->order.after(stream)) != hipSuccess) return hip_fail(h, e, "hipEventRecord");
     return HRMS_OK;
 }
 
@@ -1074,6 +1194,8 @@ int hrms_run_2d(hrms_handle h, const hrms_run2d_args* a, void* hip_stream)
     Plan2D* P = nullptr;
     st = get_plan_2d(h, a, stream, &P);
     if (st != HRMS_OK) return st;
+    if ((e = P->order.before(stream)) != hipSuccess) return hip_fail(h, e, "stream ordering");
+    UseGuard use(P->order, stream);
     const bool compute = a->stats_mode == HRMS_STATS_COMPUTE;
     if (compute) {
         StatsParams sp{a->x, (const SpecDesc*)P->d_rows.p, (const Seg*)P->d_segs.p,
@@ -1113,6 +1235,7 @@ int hrms_run_2d(hrms_handle h, const hrms_run2d_args* a, void* hip_stream)
         if ((e = launch_hrms2d(a->variant, a->dtype, rp, stream)) != hipSuccess)
             return hip_fail(h, e, "2D harmonic-sum launch");
     }
+    if ((e = use.finish()) != hipSuccess) return hip_fail(h, e, "hipEventRecord");
     return HRMS_OK;
 }
 
@@ -1125,9 +1248,13 @@ int hrms_quantize(hrms_handle h, const hrms_quantize_args* a, void* hip_stream)
     hipError_t e = hipSetDevice(h->device);
     if (e != hipSuccess) return hip_fail(h, e, "hipSetDevice");
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    if (a->stats_mode == HRMS_STATS_PROVIDED && (st = check_provided_q(h, a, stream)) != HRMS_OK)
+        return st;
     PlanQ* P = nullptr;
     st = get_plan_q(h, a, stream, &P);
     if (st != HRMS_OK) return st;
+    if ((e = P->order.before(stream)) != hipSuccess) return hip_fail(h, e, "stream ordering");
+    UseGuard use(P->order, stream);
     const bool compute = a->stats_mode == HRMS_STATS_COMPUTE;
     if (compute) {
         StatsParams sp{a->x, (const SpecDesc*)P->d_spec.p, (const Seg*)P->d_segs.p,
@@ -1155,6 +1282,7 @@ int hrms_quantize(hrms_handle h, const hrms_quantize_args* a, void* hip_stream)
     qp.nsegs = (int32_t)P->segs.size();
     if ((e = launch_quantize(a->dtype, qp, stream)) != hipSuccess)
         return hip_fail(h, e, "quantisation launch");
+    if ((e = use.finish()) != hipSuccess) return hip_fail(h, e, "hipEventRecord");
     return HRMS_OK;
 }
 

@@ -1598,9 +1598,12 @@ __global__ __launch_bounds__(64) void k_quant_consts(const QuantConstParams p)
         mu = p.stats[2 * (int64_t)s];
         sigma = p.stats[2 * (int64_t)s + 1];
     }
-    p.stats_out[2 * (int64_t)s] = 1.0;
-    p.stats_out[2 * (int64_t)s + 1] = sigma / mu;
-    p.inv_mu[s] = (float)(1.0 / mu);
+    // a spectrum whose mean is not a positive finite number cannot be scaled
+    // to unit mean: it is stored unscaled, with its own statistics
+    const bool scalable = mu > 0.0 && mu <= 1.79769313486231570e308;
+    p.stats_out[2 * (int64_t)s] = scalable ? 1.0 : mu;
+    p.stats_out[2 * (int64_t)s + 1] = scalable ? sigma / mu : sigma;
+    p.inv_mu[s] = scalable ? (float)(1.0 / mu) : 1.0f;
 }
 
 __device__ __forceinline__ uint16_t to_f16_sat(float v)

@@ -245,6 +245,39 @@ def _torch_dtype_code(t):
     return m[t.dtype]
 
 
+def _check_input(x, offsets) -> None:
+    """The library builds buffer resources from the offsets and cannot see
+    the tensor behind a pointer: x must be a contiguous device tensor holding
+    every bin the offsets name."""
+    import torch
+    if not isinstance(x, torch.Tensor):
+        raise TypeError("x must be a torch tensor")
+    if x.device.type != "cuda":
+        raise ValueError(f"x must be on a HIP device, not {x.device}")
+    _check_input_layout(x, offsets)
+
+
+def _check_input_layout(x, offsets) -> None:
+    if not x.is_contiguous():
+        raise ValueError("x must be contiguous")
+    if offsets.ndim != 1 or offsets.size < 2:
+        raise ValueError("offsets must hold n_spectra + 1 >= 2 values")
+    if x.numel() < int(offsets[-1]):
+        raise ValueError(f"x holds {x.numel()} bins, the offsets name {int(offsets[-1])}")
+
+
+def _check_stats(stats, shape, device) -> None:
+    import torch
+    if not isinstance(stats, torch.Tensor) or stats.dtype != torch.float64:
+        raise TypeError("stats must be a float64 torch tensor")
+    if tuple(stats.shape) != tuple(shape):
+        raise ValueError(f"stats must have shape {tuple(shape)}, not {tuple(stats.shape)}")
+    if stats.device != device:
+        raise ValueError(f"stats must be on {device}, not {stats.device}")
+    if not stats.is_contiguous():
+        raise ValueError("stats must be contiguous")
+
+
 class Batch1D:
     """Device buffers of one 1D batch call. ``offsets`` and ``hmax`` stay on the
     host (numpy); ``x`` and every output are torch tensors on the device."""
@@ -255,6 +288,9 @@ class Batch1D:
         self.x = x
         self.offsets = np.ascontiguousarray(offsets, np.int64)
         n = self.offsets.size - 1
+        _check_input(x, self.offsets)
+        if stats is not None:
+            _check_stats(stats, (n, 2), x.device)
         if np.isscalar(hmax):
             self.hmax_arr = None
             self.hmax_all = int(hmax)

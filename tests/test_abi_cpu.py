@@ -178,3 +178,31 @@ def test_exhaustive_path_sum_is_h_only_and_1d_only():
     a = H.hrms_run2d_args()
     a.nf, a.zmax, a.hmax, a.variant, a.ld, a.out_mask = 1000, 3, 16, H.HRMS_OPT, 1000, 1
     assert H.lib().hrms_layout_2d(C.byref(a), None, None) == H.HRMS_E_UNSUPPORTED
+
+
+def test_binding_rejects_host_short_or_strided_inputs():
+    """Batch1D refuses what the C ABI cannot see behind a pointer: a tensor
+    off the device, a strided view, fewer bins than the offsets name, and
+    provided statistics of the wrong shape or type."""
+    import torch
+    offsets = np.array([0, 100, 250], np.int64)
+    with pytest.raises(ValueError, match="HIP device"):
+        H.Batch1D(torch.zeros(250), offsets, H.HRMS_MAX, 8)
+    with pytest.raises(TypeError):
+        H.Batch1D(np.zeros(250, np.float32), offsets, H.HRMS_MAX, 8)
+    # the remaining checks, on host tensors standing in for device ones
+    H._check_input_layout(torch.zeros(250), offsets)
+    with pytest.raises(ValueError, match="contiguous"):
+        H._check_input_layout(torch.zeros(500)[::2], offsets)
+    with pytest.raises(ValueError, match="bins"):
+        H._check_input_layout(torch.zeros(249), offsets)
+    with pytest.raises(ValueError, match="offsets"):
+        H._check_input_layout(torch.zeros(10), np.array([0], np.int64))
+    dev = torch.device("cpu")
+    H._check_stats(torch.zeros((2, 2), dtype=torch.float64), (2, 2), dev)
+    with pytest.raises(TypeError):
+        H._check_stats(torch.zeros((2, 2), dtype=torch.float32), (2, 2), dev)
+    with pytest.raises(ValueError, match="shape"):
+        H._check_stats(torch.zeros((2, 3), dtype=torch.float64), (2, 2), dev)
+    with pytest.raises(ValueError, match="contiguous"):
+        H._check_stats(torch.zeros((2, 4), dtype=torch.float64)[:, ::2], (2, 2), dev)

@@ -167,3 +167,76 @@ def test_long_spectrum_sampled(handle, variant):
     out = fetch(b)
     idx = sample_indices(N, 32, 4000, np.random.default_rng(variant))
     check_spectrum(b, out, seen, 0, variant, 32, idx=idx, label="long")
+
+
+def _same_or_both_nan(got, exp):
+    got = np.asarray(got, np.float64)
+    exp = np.asarray(exp, np.float64)
+    return (got == exp) | (np.isnan(got) & np.isnan(exp))
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_nan_and_inf_bins(handle, variant):
+    """Non-finite bins are outside the method's domain; the run must still
+    finish and give exactly what the definitions give in IEEE arithmetic:
+    comparisons with NaN are false, so a Max window keeps its first bin's NaN
+    and skips later ones, Greedy stays on the left bin of a NaN pair, and a
+    sum that meets NaN or +inf carries it. Statistics are provided (those of
+    the clean spectrum), so the constants stay finite."""
+    from paper_1812_02647_amd import hrms as H
+    import torch
+    n = 20011
+    x = synth.exponential(99, 0, n).astype(np.float32)
+    mu, sd = O.stats(x.astype(np.float64))
+    for pos in (0, 1, 7, 64, 65, 129, 500, 1001, 4000, 9999, n - 1):
+        x[pos] = np.nan
+    for pos in (3, 66, 250, 2048, 7777, n - 2):
+        x[pos] = np.inf
+    offsets = np.array([0, n], np.int64)
+    xd, seen = to_device_input(x, "f32")
+    case_log(f"nan_and_inf_bins variant={NAMES[variant]} N={n} hmax=32")
+    st = torch.tensor([[mu, sd]], dtype=torch.float64, device="cuda")
+    b = run_1d(handle, xd, offsets, variant, 32, stats=st)
+    out = fetch(b)
+    h32, ms32, bh32, _ = O.hrms_1d(seen, variant, 32, f32=True, mu=mu, sigma=sd)
+    for l in range(6):
+        ln = n if variant == 0 else n >> l
+        got = out["h"][int(b.plane_offsets[0, l]):int(b.plane_offsets[0, l]) + ln]
+        ok = _same_or_both_nan(got, h32[l][:ln])
+        assert ok.all(), (l, np.nonzero(~ok)[0][:5])
+    assert _same_or_both_nan(out["max_snr"], ms32).all()
+    assert np.array_equal(out["best_h"], bh32)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_two_streams_same_signature(variant):
+    """Two batches with the same offsets (so the same cached plan and its
+    scratch) but different bins, run alternately on two streams of one handle
+    without synchronising in between: each result equals the oracle."""
+    import torch
+    from paper_1812_02647_amd import hrms as H
+    lengths = [1 << 17, 70001, 1 << 16, 40000]
+    xa, offsets, _ = synth.batch(len(lengths), lengths, seed=401, comb_fraction=0.0)
+    xb, offsets_b, _ = synth.batch(len(lengths), lengths, seed=402, comb_fraction=0.0)
+    assert np.array_equal(offsets, offsets_b)
+    da, seen_a = to_device_input(xa, "f32")
+    db, seen_b = to_device_input(xb, "f32")
+    h = H.hrms_create(0)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    try:
+        case_log(f"two_streams_same_signature variant={NAMES[variant]} lengths={lengths}")
+        ba = H.Batch1D(da, offsets, variant, 32)
+        bb = H.Batch1D(db, offsets, variant, 32)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            ba.run(h, s1)
+            bb.run(h, s2)
+        torch.cuda.synchronize()
+        for b, seen in ((ba, seen_a), (bb, seen_b)):
+            out = fetch(b)
+            for s in range(len(lengths)):
+                idx = sample_indices(lengths[s], 32, 2000, np.random.default_rng(s))
+                check_spectrum(b, out, seen, s, variant, 32, idx=idx, check_f64=False,
+                               label="two-streams")
+    finally:
+        H.hrms_destroy(h)

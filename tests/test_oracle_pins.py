@@ -179,7 +179,7 @@ def test_eq1_at_h_times_m_equals_freqbin_at_m():
 
 # --------------------------------------------------------------------------
 # Exhaustive enumeration on tiny inputs (the "optimal" sum of Sec. 1 performs
-# all possible sums; Greedy and freq-bin are single paths of it, Max bounds it).
+# every path sum; Greedy and freq-bin are single paths of it, Max bounds it).
 # --------------------------------------------------------------------------
 
 def all_path_sums(x, n, H):
