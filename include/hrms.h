@@ -236,6 +236,29 @@ int hrms_layout_2d(const hrms_run2d_args* a, int64_t* plane_offsets, int64_t* h_
  * afterwards (environment HRMS_NO_GRAPH=1 enqueues them directly instead). */
 int hrms_run_1d(hrms_handle h, const hrms_run1d_args* a, void* hip_stream);
 
+/* hrms_run_1d for callers that cannot allocate device memory: code that runs
+ * while a HIP graph is being captured, tight serving loops, harnesses that
+ * forbid hipMalloc. Same arguments, validation and results (bit for bit) as
+ * hrms_run_1d; it calls no hipMalloc, hipFree or other allocating routine.
+ *   - Its plan tables (spectrum descriptors, tile queues, statistics segments)
+ *     and per-call scratch (queue counters, statistics partials, SNR
+ *     constants) live in one static device array of 48 MiB per GPU, held from
+ *     the first hrms_create on that GPU until the process ends. A batch whose
+ *     plan needs more (about 32 bytes per tile of 2048-4096 outputs, plus
+ *     about 200 bytes per spectrum and 32 bytes per 65536 bins; 1000 spectra
+ *     of 2^21 bins fit in every variant) is rejected with HRMS_E_INVAL before
+ *     anything is enqueued.
+ *   - Every call on a GPU, from any handle, shares that GPU's array, which
+ *     keeps the last call's contents: calls that overlap on one GPU (on
+ *     different streams, or from different threads) race and give wrong
+ *     results. Order them on one stream.
+ *   - Launches are enqueued directly (no graph). When the previous call on
+ *     the GPU used another batch signature, the tables are first copied from
+ *     host memory into the array on `hip_stream`.
+ *   - The handle keeps the host side of its 4 latest batch signatures; making
+ *     room for a fifth waits until the device is idle. */
+int hrms_run_1d_noalloc(hrms_handle h, const hrms_run1d_args* a, void* hip_stream);
+
 /* Picks the fastest compiled launch shape (threads per workgroup, outputs per
  * thread, LDS chunk or 0 for the gathered form, and the lowest top level of the
  * bands handed to a second launch of the LDS form, 0 for none) for batches

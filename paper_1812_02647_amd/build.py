@@ -20,7 +20,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhrms.so")
 
-HIP_SOURCES = ["hrms_kernels.hip", "hrms_abi.cpp"]
+HIP_SOURCES = ["hrms_kernels.hip", "hrms_abi.cpp", "hrms_noalloc.hip"]
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
     "-O3",

@@ -8,12 +8,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -130,6 +132,7 @@ struct Plan1D {
     std::vector<int32_t> seg_first;
     int grid = 0, grid_top = 0;
     int nqueues = 1;
+    uint64_t serial = 0;   // process-unique, names the tables in the no-alloc scratch
     // device
     DeviceBuf d_spec, d_tiles, d_qbeg, d_tiles_top, d_qbeg_top, d_segs, d_seg_first, d_partial,
         d_consts, d_counter;
@@ -191,6 +194,11 @@ struct hrms_ctx {
     hipStream_t capture = nullptr;   // private stream for graph capture
     bool graphs = true;
     std::vector<std::unique_ptr<Plan1D>> plans;   // most recent last
+    // host-only plans of hrms_run_1d_noalloc (their tables live in the
+    // device's static scratch), most recent last
+    std::vector<std::unique_ptr<Plan1D>> na_plans;
+    void* scratch = nullptr;             // this device's copy of the no-alloc scratch
+    hipError_t scratch_status = hipSuccess;
     std::unique_ptr<Plan2D> plan2d;
     std::unique_ptr<PlanQ> planq;
 };
@@ -1026,6 +1034,131 @@ int run_1d_with(hrms_ctx* h, const hrms_run1d_args* a, hipStream_t stream, const
     return HRMS_OK;
 }
 
+// ---------------------------------------------------------------------------
+// The entry point that allocates nothing: host plans only; the plan's tables
+// and the per-call scratch live in the device's static scratch array
+// ---------------------------------------------------------------------------
+
+std::atomic<uint64_t> g_plan_serial{0};
+
+// Which plan's tables each device's static scratch holds (0: none). Every
+// write of the tables goes through run_1d_noalloc, so a plan whose serial is
+// recorded here needs no upload.
+std::mutex g_owner_mu;
+std::map<int, uint64_t> g_scratch_owner;
+
+struct ScratchLayout {
+    size_t counters, consts, partial, spec, qbeg, qbeg_top, tiles, tiles_top, segs, seg_first;
+    size_t total;
+};
+
+ScratchLayout scratch_layout(const Plan1D& P)
+{
+    ScratchLayout L{};
+    size_t off = 0;
+    auto take = [&off](size_t bytes) {
+        const size_t at = off;
+        off += (bytes + 255) / 256 * 256;
+        return at;
+    };
+    const size_t ns = P.spec.size();
+    L.counters = take(sizeof(unsigned int) * kCounterSlots);
+    L.consts = take(ns * kMaxLevels * sizeof(LevelConst));
+    L.partial = take(P.segs.size() * 2 * sizeof(double));
+    L.spec = take(ns * sizeof(SpecDesc));
+    L.qbeg = take(P.qbeg.size() * sizeof(int32_t));
+    L.qbeg_top = take(P.qbeg_top.size() * sizeof(int32_t));
+    L.tiles = take(P.tiles.size() * sizeof(TileRec));
+    L.tiles_top = take(P.tiles_top.size() * sizeof(TileRec));
+    L.segs = take(P.segs.size() * sizeof(Seg));
+    L.seg_first = take(P.seg_first.size() * sizeof(int32_t));
+    L.total = off;
+    return L;
+}
+
+PlanDev plan_dev_at(char* base, const ScratchLayout& L)
+{
+    return PlanDev{(const SpecDesc*)(base + L.spec),      (const TileRec*)(base + L.tiles),
+                   (const int32_t*)(base + L.qbeg),       (const TileRec*)(base + L.tiles_top),
+                   (const int32_t*)(base + L.qbeg_top),   (const Seg*)(base + L.segs),
+                   (const int32_t*)(base + L.seg_first),  (double*)(base + L.partial),
+                   (LevelConst*)(base + L.consts),        (unsigned int*)(base + L.counters)};
+}
+
+// Host plan of the no-alloc entry point (it never gets device buffers).
+int get_plan_1d_host(hrms_ctx* c, const hrms_run1d_args* a, const Shape1D& shape, Plan1D** out)
+{
+    for (size_t k = 0; k < c->na_plans.size(); ++k) {
+        if (same_signature(*c->na_plans[k], a, shape)) {
+            std::unique_ptr<Plan1D> p = std::move(c->na_plans[k]);
+            c->na_plans.erase(c->na_plans.begin() + (long)k);
+            c->na_plans.push_back(std::move(p));
+            *out = c->na_plans.back().get();
+            return HRMS_OK;
+        }
+    }
+    std::unique_ptr<Plan1D> p(new (std::nothrow) Plan1D());
+    if (!p) return fail(c, HRMS_E_NOMEM, "host allocation failed");
+    const int st = plan_host_1d(c, a, shape, p.get());
+    if (st != HRMS_OK) return st;
+    p->serial = ++g_plan_serial;
+    if ((int)c->na_plans.size() >= kPlanCache) {
+        // the evicted plan's host tables may still be the source of a queued
+        // copy: the device finishes its work before they are freed
+        (void)hipDeviceSynchronize();
+        c->na_plans.erase(c->na_plans.begin());
+    }
+    c->na_plans.push_back(std::move(p));
+    *out = c->na_plans.back().get();
+    return HRMS_OK;
+}
+
+template <typename T>
+hipError_t copy_section(char* base, size_t off, const std::vector<T>& v, hipStream_t s)
+{
+    if (v.empty()) return hipSuccess;
+    return hipMemcpyAsync(base + off, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+}
+
+int run_1d_noalloc(hrms_ctx* h, const hrms_run1d_args* a, hipStream_t stream)
+{
+    if (h->scratch_status != hipSuccess || !h->scratch)
+        return hip_fail(h, h->scratch_status != hipSuccess ? h->scratch_status : hipErrorInvalidSymbol,
+                        "device address of the no-alloc scratch");
+    const Shape1D shape = shape_for(h, a);
+    Plan1D* P = nullptr;
+    int st = get_plan_1d_host(h, a, shape, &P);
+    if (st != HRMS_OK) return st;
+    const ScratchLayout L = scratch_layout(*P);
+    if (L.total > kNoallocScratchBytes)
+        return fail(h, HRMS_E_INVAL,
+                    "the batch needs " + std::to_string(L.total) +
+                        " bytes of device scratch; hrms_run_1d_noalloc holds at most " +
+                        std::to_string(kNoallocScratchBytes));
+    char* base = static_cast<char*>(h->scratch);
+    hipError_t e = hipSuccess;
+    {
+        std::lock_guard<std::mutex> lock(g_owner_mu);
+        uint64_t& owner = g_scratch_owner[h->device];
+        if (owner != P->serial) {
+            owner = 0;
+            if ((e = copy_section(base, L.spec, P->spec, stream)) == hipSuccess &&
+                (e = copy_section(base, L.qbeg, P->qbeg, stream)) == hipSuccess &&
+                (e = copy_section(base, L.qbeg_top, P->qbeg_top, stream)) == hipSuccess &&
+                (e = copy_section(base, L.tiles, P->tiles, stream)) == hipSuccess &&
+                (e = copy_section(base, L.tiles_top, P->tiles_top, stream)) == hipSuccess &&
+                (e = copy_section(base, L.segs, P->segs, stream)) == hipSuccess &&
+                (e = copy_section(base, L.seg_first, P->seg_first, stream)) == hipSuccess)
+                owner = P->serial;
+        }
+    }
+    if (e != hipSuccess) return hip_fail(h, e, "copying the plan into the static scratch");
+    // the queue counters and the candidate count are cleared by the constants kernel
+    if ((e = enqueue_1d(a, P, plan_dev_at(base, L), shape, stream)) != hipSuccess)
+        return hip_fail(h, e, "launch");
+    return HRMS_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1078,6 +1211,9 @@ int hrms_create(hrms_handle* out, int device_ordinal, const char* tune_cache_pat
         c->tune_path = tune_cache_path;
         load_tune(c);
     }
+    // device address of this device's copy of the no-alloc scratch (looked up
+    // once per device, with the device current)
+    c->scratch_status = noalloc_scratch(device_ordinal, &c->scratch);
     *out = c;
     return HRMS_OK;
 }
@@ -1090,6 +1226,7 @@ int hrms_destroy(hrms_handle h)
     (void)hipSetDevice(h->device);
     (void)hipDeviceSynchronize();
     h->plans.clear();
+    h->na_plans.clear();
     h->plan2d.reset();
     h->planq.reset();
     if (h->capture) (void)hipStreamDestroy(h->capture);
@@ -1125,6 +1262,17 @@ int hrms_run_1d(hrms_handle h, const hrms_run1d_args* a, void* hip_stream)
     hipError_t e = hipSetDevice(h->device);
     if (e != hipSuccess) return hip_fail(h, e, "hipSetDevice");
     return run_1d_with(h, a, static_cast<hipStream_t>(hip_stream), shape_for(h, a), h->graphs);
+}
+
+int hrms_run_1d_noalloc(hrms_handle h, const hrms_run1d_args* a, void* hip_stream)
+{
+    if (!h) return fail(nullptr, HRMS_E_INVAL, "handle is NULL");
+    h->err.clear();
+    int st = validate_1d(h, a, true);
+    if (st != HRMS_OK) return st;
+    hipError_t e = hipSetDevice(h->device);
+    if (e != hipSuccess) return hip_fail(h, e, "hipSetDevice");
+    return run_1d_noalloc(h, a, static_cast<hipStream_t>(hip_stream));
 }
 
 int hrms_autotune_1d(hrms_handle h, const hrms_run1d_args* a, void* hip_stream, int reps,

@@ -169,4 +169,12 @@ hipError_t launch_peaks(const PeakParams& p, hipStream_t s);
 hipError_t launch_quant_consts(const QuantConstParams& p, hipStream_t s);
 hipError_t launch_quantize(int dtype, const QuantParams& p, hipStream_t s);
 
+// Static device scratch of hrms_run_1d_noalloc, one copy per GPU
+// (hrms_noalloc.hip): 48 MiB holds the plan of 1000 spectra of 2^21 bins in
+// every variant and launch shape.
+constexpr size_t kNoallocScratchBytes = size_t(48) << 20;
+// Device address of `device`'s copy, looked up once per device with that
+// device current (later calls return the stored address and status).
+hipError_t noalloc_scratch(int device, void** ptr);
+
 }  // namespace hrms

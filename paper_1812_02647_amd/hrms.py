@@ -33,7 +33,7 @@ VARIANTS = {"eq1": HRMS_EQ1, "max": HRMS_MAX, "freqbin": HRMS_FREQBIN, "greedy":
 DTYPES = {"f32": HRMS_F32, "f16": HRMS_F16, "bf16": HRMS_BF16}
 
 EXPORTED = ["hrms_create", "hrms_destroy", "hrms_layout_1d", "hrms_layout_2d", "hrms_run_1d",
-            "hrms_autotune_1d", "hrms_run_2d", "hrms_quantize", "hrms_strerror",
+            "hrms_run_1d_noalloc", "hrms_autotune_1d", "hrms_run_2d", "hrms_quantize", "hrms_strerror",
             "hrms_last_error"]
 
 
@@ -135,6 +135,8 @@ def lib():
         L.hrms_layout_2d.restype = i32
         L.hrms_run_1d.argtypes = [vp, C.POINTER(hrms_run1d_args), vp]
         L.hrms_run_1d.restype = i32
+        L.hrms_run_1d_noalloc.argtypes = [vp, C.POINTER(hrms_run1d_args), vp]
+        L.hrms_run_1d_noalloc.restype = i32
         L.hrms_autotune_1d.argtypes = [vp, C.POINTER(hrms_run1d_args), vp, i32,
                                        C.POINTER(C.c_int32)]
         L.hrms_autotune_1d.restype = i32
@@ -195,6 +197,10 @@ def hrms_layout_2d(args: hrms_run2d_args):
 
 def hrms_run_1d(handle, args: hrms_run1d_args, stream=None) -> None:
     _check(lib().hrms_run_1d(handle, C.byref(args), _stream_ptr(stream)), handle)
+
+
+def hrms_run_1d_noalloc(handle, args: hrms_run1d_args, stream=None) -> None:
+    _check(lib().hrms_run_1d_noalloc(handle, C.byref(args), _stream_ptr(stream)), handle)
 
 
 def hrms_autotune_1d(handle, args: hrms_run1d_args, stream=None, reps: int = 3):
@@ -338,6 +344,10 @@ class Batch1D:
 
     def run(self, handle, stream=None):
         hrms_run_1d(handle, self.args, stream)
+        return self
+
+    def run_noalloc(self, handle, stream=None):
+        hrms_run_1d_noalloc(handle, self.args, stream)
         return self
 
     def candidates(self):
