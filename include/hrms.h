@@ -11,7 +11,8 @@
  *                                  the larger of x(k n + j), x(k n + j + 1) and
  *                                  moves j up by one when the right bin is
  *                                  strictly larger
- *   HRMS_OPT      Sec. 1 ("optimal" sum performing every possible sum), 1D,
+ *   HRMS_OPT      Sec. 1 (the sum it calls optimal, which tries every bin
+ *                                  combination; no definition given), 1D,
  *                                  h only: the largest sum over every offset
  *                                  path eq. (4) could follow (j_1 = 0, each
  *                                  later j equal to or one above the previous),

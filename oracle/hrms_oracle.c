@@ -12,8 +12,9 @@
  *   - Max HRMS, eq. (2), Sec. 2
  *   - freq-bin HRMS, eq. (3), Sec. 2
  *   - Greedy HRMS, eq. (4) and the sentence after it, Sec. 2
- *   - exhaustive-path ("optimal") sum, named in Sec. 1 as performing every
- *     possible sum; the reading used here is stated at sum_opt_paths
+ *   - exhaustive-path ("optimal") sum: Sec. 1 names an optimal sum that tries
+ *     every combination of bins without defining it; the reading used here is
+ *     stated at sum_opt_paths
  *   - 2D harmonic sum after the acceleration search: named in the abstract and
  *     Sec. 1 but not defined; the reading used here is stated at oracle_2d_sum.
  *   - SNR (Sec. 3) is reported but not defined; the reading used here is stated

@@ -11,8 +11,10 @@ The figures themselves are not available, so the prose claims are checked:
 The paper also reports an averaged loss of about 40% for Max and a response
 flat across the bin. With the SNR read here as a standardisation against the
 exact null moments of each variant (the Max null includes the bias of taking
-maxima), Max loses far less and is not flat; only "Max below the standard sum"
-is asserted, and the measured figures are reported by the device study.
+maxima), Max loses far less and is not flat. The last two tests hold the
+adopted reading to the figures it gives and show that no other reading of the
+SNR (raw sums, eq. (1)'s null for every variant, empirical or robust moments
+of each level), nor Max's window taken as printed, reaches the Max claims.
 
 The recovered SNR is the largest max-SNR output near where a variant places the
 pulsar (fundamental bins around floor(k) for eq. (2)-(4); round(H k) for every
@@ -93,3 +95,44 @@ def test_averaged_losses(sweep_study):
     assert 0.70 <= fb / eq1 <= 0.90, avg          # "about 20%" lower
     assert abs(gr / eq1 - 1.0) <= 0.15, avg       # Greedy similar to standard
     assert mx < eq1, avg
+
+
+# --------------------------------------------------------------------------
+# The SNR that Sec. 3 reports is not defined there. Every plausible reading
+# (tests/snr_readings.py) is applied to the same sums; the adopted one
+# (standardisation against the exact null of each variant) is held to the
+# figures it gives, and no reading -- nor Max's window taken as printed --
+# gives Max the averaged loss of about 40% or a response flat across the bin
+# that the paper reports, so that gap is a property of the paper's unstated
+# set-up, not of the reading taken here.
+# --------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def readings():
+    from tests import snr_readings as R
+    xb, ob, mb = synth.sensitivity_set()
+    xs, os_, ms = synth.frequency_sweep_set()
+    d = np.array([m[1] for m in mb])
+    adopted = R.claims(R.study(xb, ob, mb), d, R.study(xs, os_, ms))
+    literal = R.claims(R.study(xb, ob, mb, literal_max=True), d,
+                       R.study(xs, os_, ms, literal_max=True))
+    return adopted, literal
+
+
+def test_adopted_snr_reading_measured_figures(readings):
+    s = readings[0]["standardised"]
+    assert 0.28 <= s["freqbin_off_over_on"] <= 0.36, s     # measured 0.318
+    assert 0.70 <= s["max_off_over_on"] <= 0.77, s          # measured 0.734
+    assert 0.52 <= s["max_flatness"] <= 0.60, s             # measured 0.556
+    assert 0.88 <= s["avg_over_eq1"]["max"] <= 0.94, s      # measured 0.911
+    assert 0.83 <= s["avg_over_eq1"]["freqbin"] <= 0.89, s  # measured 0.858
+    assert 0.90 <= s["avg_over_eq1"]["greedy"] <= 0.95, s   # measured 0.927
+
+
+def test_no_snr_reading_gives_max_a_forty_percent_loss(readings):
+    for table in readings:
+        for name, r in table.items():
+            assert r["avg_over_eq1"]["max"] > 0.85, (name, r)
+            assert r["max_flatness"] < 0.80, (name, r)
+            # freq-bin's off-bin loss of more than half holds under every reading
+            assert r["freqbin_off_over_on"] < 0.5, (name, r)
