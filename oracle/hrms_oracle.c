@@ -53,6 +53,7 @@
 #define OV_FREQBIN 2
 #define OV_GREEDY 3
 #define OV_OPT 4
+#define OV_GREEDY_FZ 5   /* 2D only: Greedy with fdot drift */
 
 #define OE_OK 0
 #define OE_INVAL (-1)
@@ -271,6 +272,12 @@ int oracle_stats(const double* x, int64_t n, double* mu, double* sigma)
  *   eq. (4): the first term is one bin; each later term is the maximum of two
  *       fresh bins (mean mu + sigma/2, variance 5/4 sigma^2), so
  *       E S = mu + (H-1)(mu + sigma/2), Var S = sigma^2 (1 + 5/4 (H-1)).
+ *   Greedy with fdot drift (2D, z != 0): each later term is the maximum of
+ *       four fresh bins (two rows by two columns), so
+ *       E S = mu + (H-1)(mu + 13/12 sigma), Var S = sigma^2 (1 + 205/144 (H-1));
+ *       its z = 0 row cannot drift in fdot and takes the eq. (4) constants.
+ *   "Fresh" assumes the bins a path may read at different harmonics are
+ *   distinct, which holds for fundamentals m >= H away from the plane's edge.
  *
  * Written out for level H in binary64, in this operation order, then rounded
  * once: m32 = (float)m, q32 = (float)(1/s), and q32 = 0 when s = 0.
@@ -300,6 +307,12 @@ int oracle_snr_consts(int variant, double mu, double sigma, int hmax, float* m32
         } else if (variant == OV_GREEDY) {
             mean_s = mu + (double)(H - 1) * (mu + 0.5 * sigma);
             var_s = (sigma * sigma) * (1.0 + 1.25 * (double)(H - 1));
+        } else if (variant == OV_GREEDY_FZ) {
+            /* each later term is the largest of four fresh bins: mean
+             * mu + sigma (Hn_4 - 1) = mu + 13/12 sigma, variance
+             * Psi_4 sigma^2 = 205/144 sigma^2 */
+            mean_s = mu + (double)(H - 1) * (mu + (13.0 / 12.0) * sigma);
+            var_s = (sigma * sigma) * (1.0 + (205.0 / 144.0) * (double)(H - 1));
         } else {
             return OE_INVAL;
         }
@@ -392,6 +405,50 @@ int oracle_hrms_1d(const double* x, int64_t N, int variant, int hmax, const int6
  * 1D. Each level is computed on its own, since the row sampled for harmonic i
  * depends on H.
  */
+/*
+ * Greedy with fdot drift (2D only). The paper names a Greedy sum on the
+ * frequency x fdot plane (abstract, Sec. 1) without defining it; it is read
+ * as eq. (4)'s step rule applied to the fdot row as well as to the column.
+ * With s = sign(z), path offsets j (column) and d (row, in fdot units)
+ * starting at 0, and rows clamped to the plane:
+ *     start at x[row_1][m];
+ *     for k = 2..H, with r0 = clamp(round(k z / H) + d), r1 = clamp(r0' + s)
+ *     where r0' = round(k z / H) + d, and c = k m + j, the candidates in this
+ *     order are x[r0][c], x[r0][c + 1], x[r1][c], x[r1][c + 1]; the first
+ *     largest is added (a later one replaces it only when strictly larger),
+ *     and j grows by one when its column is c + 1, d by s when its row is r1.
+ * The fdot of harmonic k grows in magnitude with k, so an underestimate of a
+ * signal's fdot accumulates away from zero, as an underestimate of its
+ * frequency accumulates upwards in eq. (4). At z = 0 (s = 0) the two rows
+ * coincide and the sum is eq. (4) along row z = 0. Rows are rounded halves
+ * away from zero and the candidate order is the same under z -> -z, so the
+ * sum is mirror-symmetric in z.
+ */
+static int64_t clamp_row(int64_t r, int zmax) { return r < -zmax ? -zmax : (r > zmax ? zmax : r); }
+
+static double sum_2d_greedy_fz(const double* x, int64_t ld, int zmax, int H, int64_t mbin, int z,
+                               int f32)
+{
+    const int64_t s = z > 0 ? 1 : (z < 0 ? -1 : 0);
+    int64_t j = 0, d = 0;
+    double acc = x[(round_half_away((int64_t)z, H) + zmax) * ld + mbin];
+    for (int k = 2; k <= H; ++k) {
+        const int64_t rk = round_half_away((int64_t)k * z, H);
+        const int64_t r0 = clamp_row(rk + d, zmax) + zmax;
+        const int64_t r1 = clamp_row(rk + d + s, zmax) + zmax;
+        const int64_t c = (int64_t)k * mbin + j;
+        const double cand[4] = {x[r0 * ld + c], x[r0 * ld + c + 1], x[r1 * ld + c],
+                                x[r1 * ld + c + 1]};
+        int pick = 0;
+        for (int t = 1; t < 4; ++t)
+            if (cand[t] > cand[pick]) pick = t;
+        acc = rnd(f32, acc + cand[pick]);
+        if (pick & 1) j += 1;
+        if (pick & 2) d += s;
+    }
+    return acc;
+}
+
 static double sum_2d(const double* x, int64_t ld, int zmax, int variant, int H, int64_t mbin, int z,
                      int f32)
 {
@@ -421,6 +478,7 @@ static double sum_2d(const double* x, int64_t ld, int zmax, int variant, int H, 
         }
         return acc;
     }
+    if (variant == OV_GREEDY_FZ) return sum_2d_greedy_fz(x, ld, zmax, H, mbin, z, f32);
     /* GREEDY */
     {
         int64_t row1 = round_half_away((int64_t)z, H) + zmax;
@@ -450,7 +508,9 @@ double oracle_sum_2d(const double* x, int64_t ld, int zmax, int variant, int H, 
 /*
  * For the outputs (m_k, z_k) listed in (fidx, zidx) -- or the whole plane,
  * row-major over r = z + zmax then m, when fidx is NULL -- computes every level
- * exactly as oracle_hrms_1d does, with the 2D sums above.
+ * exactly as oracle_hrms_1d does, with the 2D sums above. For Greedy with fdot
+ * drift m and q hold two sets of per-level constants: [0, levels) for z != 0,
+ * then [levels, 2 levels) for the z = 0 row.
  */
 int oracle_hrms_2d(const double* x, int64_t ld, int64_t nf, int zmax, int variant, int hmax,
                    const int64_t* fidx, const int32_t* zidx, int64_t cnt, const double* m,
@@ -458,7 +518,7 @@ int oracle_hrms_2d(const double* x, int64_t ld, int64_t nf, int zmax, int varian
 {
     int nl = oracle_num_levels(hmax);
     if (nl < 1 || nf < 1 || zmax < 0 || ld < nf || !x) return OE_INVAL;
-    if (variant < OV_EQ1 || variant > OV_GREEDY) return OE_INVAL;
+    if (variant < OV_EQ1 || variant > OV_GREEDY_FZ || variant == OV_OPT) return OE_INVAL;
     int64_t rows = 2 * (int64_t)zmax + 1;
     if (!fidx) cnt = rows * nf;
     for (int64_t k = 0; k < cnt; ++k) {
@@ -477,7 +537,9 @@ int oracle_hrms_2d(const double* x, int64_t ld, int64_t nf, int zmax, int varian
             double hv = rnd(f32, s * inv_sqrt_h(H, f32));
             if (h) h[(int64_t)l * cnt + k] = hv;
             if (m && q) {
-                double snr = snr_of(hv, m[l], q[l], f32);
+                /* Greedy with fdot drift: its z = 0 row takes the second set */
+                int c = (variant == OV_GREEDY_FZ && z == 0) ? nl + l : l;
+                double snr = snr_of(hv, m[c], q[c], f32);
                 if (l == 0 || snr > best) {
                     best = snr;
                     best_level = H;

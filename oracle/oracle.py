@@ -17,7 +17,9 @@ import subprocess
 import numpy as np
 
 EQ1, MAX, FREQBIN, GREEDY, OPT = 0, 1, 2, 3, 4
-VARIANTS = {"eq1": EQ1, "max": MAX, "freqbin": FREQBIN, "greedy": GREEDY, "opt": OPT}
+GREEDY_FZ = 5   # 2D only: Greedy with fdot drift
+VARIANTS = {"eq1": EQ1, "max": MAX, "freqbin": FREQBIN, "greedy": GREEDY, "opt": OPT,
+            "greedy_fz": GREEDY_FZ}
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "hrms_oracle.c")
@@ -186,7 +188,8 @@ def hrms_2d(x2d, zmax: int, variant: int, hmax: int, fidx=None, zidx=None, f32: 
     """All levels of plane outputs (m, z); whole plane when ``fidx`` is None.
 
     ``x2d`` has shape (2*zmax+1, nf). Whole-plane results are row-major over
-    (z + zmax, m).
+    (z + zmax, m). For GREEDY_FZ the returned constants hold two sets of
+    levels: the rows z != 0, then the row z = 0.
     """
     x2d = _f64(x2d)
     rows, nf = x2d.shape
@@ -206,6 +209,13 @@ def hrms_2d(x2d, zmax: int, variant: int, hmax: int, fidx=None, zidx=None, f32: 
             mu, sigma = stats(x2d)
         consts = snr_consts(variant, mu, sigma, hmax)
         m32, q32, m64, q64 = consts
+        if variant == GREEDY_FZ:
+            # the z = 0 row cannot drift in fdot: eq. (4)'s constants, as a
+            # second set after the drifting rows' ones
+            g32m, g32q, g64m, g64q = snr_consts(GREEDY, mu, sigma, hmax)
+            m32, q32 = np.concatenate([m32, g32m]), np.concatenate([q32, g32q])
+            m64, q64 = np.concatenate([m64, g64m]), np.concatenate([q64, g64q])
+            consts = (m32, q32, m64, q64)
         mq = (m32.astype(np.float64), q32.astype(np.float64)) if f32 else (m64, q64)
     h = np.empty((nl, cnt), np.float64)
     ms = np.empty(cnt, np.float64)

@@ -76,6 +76,26 @@ MUTATIONS = [
     ("opt paths skip the last harmonic", "        for (int k = 2; k <= H; ++k) {\n            j += (path >> (k - 2)) & 1;",
      "        for (int k = 2; k < H; ++k) {\n            j += (path >> (k - 2)) & 1;"),
     ("scale uses binary64 1/mu", "double inv = (double)(float)(1.0 / mu);", "double inv = 1.0 / mu;"),
+    ("2d fdot-drift Greedy drifts toward zero", "const int64_t s = z > 0 ? 1 : (z < 0 ? -1 : 0);",
+     "const int64_t s = z > 0 ? -1 : (z < 0 ? 1 : 0);"),
+    ("2d fdot-drift Greedy never drifts in fdot", "        if (pick & 2) d += s;\n", ""),
+    ("2d fdot-drift Greedy never steps in frequency", "        if (pick & 1) j += 1;\n", ""),
+    ("2d fdot-drift Greedy takes ties to the later candidate",
+     "            if (cand[t] > cand[pick]) pick = t;", "            if (cand[t] >= cand[pick]) pick = t;"),
+    ("2d fdot-drift Greedy clamps one row short at the top",
+     "return r < -zmax ? -zmax : (r > zmax ? zmax : r);",
+     "return r < -zmax ? -zmax : (r > zmax - 1 ? zmax - 1 : r);"),
+    ("2d fdot-drift Greedy reads the row of harmonic k-1",
+     "const int64_t rk = round_half_away((int64_t)k * z, H);",
+     "const int64_t rk = round_half_away((int64_t)(k - 1) * z, H);"),
+    ("2d fdot-drift Greedy z = 0 row takes the drifting constants",
+     "int c = (variant == OV_GREEDY_FZ && z == 0) ? nl + l : l;", "int c = l;"),
+    ("2d fdot-drift Greedy mean of a max of four as of two",
+     "mean_s = mu + (double)(H - 1) * (mu + (13.0 / 12.0) * sigma);",
+     "mean_s = mu + (double)(H - 1) * (mu + 0.5 * sigma);"),
+    ("2d fdot-drift Greedy variance of a max of four as of two",
+     "var_s = (sigma * sigma) * (1.0 + (205.0 / 144.0) * (double)(H - 1));",
+     "var_s = (sigma * sigma) * (1.0 + 1.25 * (double)(H - 1));"),
 ]
 
 

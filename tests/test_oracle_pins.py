@@ -486,6 +486,148 @@ def test_2d_harmonic_reads_the_nearest_row(variant):
             assert hit == want, (i0, r, hit, want)
 
 
+# --------------------------------------------------------------------------
+# 2D Greedy with fdot drift (eq. (4)'s step rule applied to the fdot row too).
+# --------------------------------------------------------------------------
+
+def _fz_paths(x, zmax, H, m, z):
+    """Sums of every path that the fdot-drifting Greedy could follow at output
+    (m, z) of level H: column offsets j and row offsets d start at 0 and each
+    harmonic k = 2..H moves j by 0 or 1 and d by 0 or sign(z); the row of
+    harmonic k is round(k z / H) + d, clamped to the plane. Enumerated in
+    binary64 by brute force (4^(H - 1) paths)."""
+    s = (z > 0) - (z < 0)
+    out = []
+
+    def rnd(k, zz):
+        a, b = k * zz, H
+        return (2 * a + b) // (2 * b) if a >= 0 else -((-2 * a + b) // (2 * b))
+
+    def clamp(r):
+        return max(-zmax, min(zmax, r))
+
+    def walk(k, j, d, acc):
+        if k > H:
+            out.append(acc)
+            return
+        for dj in (0, 1):
+            for dd in (0, s):
+                row = clamp(rnd(k, z) + d + dd) + zmax
+                walk(k + 1, j + dj, d + dd, acc + x[row, k * m + j + dj])
+    walk(2, 0, 0, x[rnd(1, z) + zmax, m])
+    return out
+
+
+def test_2d_greedy_fz_identity_mirror_and_reduction():
+    zmax, nf = 6, 700
+    rng = np.random.default_rng(5)
+    # small integers: many ties, so the tie order is exercised too
+    x = rng.integers(0, 6, size=(2 * zmax + 1, nf)).astype(np.float64)
+    h, _, _, _ = O.hrms_2d(x, zmax, O.GREEDY_FZ, 16, want_snr=False)
+    h = h.reshape(len(O.levels(16)), 2 * zmax + 1, nf)
+    assert np.array_equal(h[0], x)
+    # z = 0 cannot drift in fdot: eq. (4) along row z = 0
+    h1, _, _, _ = O.hrms_1d(x[zmax], O.GREEDY, 16, want_snr=False)
+    assert np.array_equal(h[:, zmax, :], h1, equal_nan=True)
+    hm, _, _, _ = O.hrms_2d(x[::-1].copy(), zmax, O.GREEDY_FZ, 16, want_snr=False)
+    assert np.array_equal(hm.reshape(h.shape)[:, ::-1, :], h, equal_nan=True)
+    for l, H in enumerate(O.levels(16)):
+        assert np.all(np.isnan(h[l][:, nf // H:])) and not np.any(np.isnan(h[l][:, :nf // H]))
+    # constant plane
+    c = np.full((2 * zmax + 1, 256), 1.5)
+    hc, _, _, _ = O.hrms_2d(c, zmax, O.GREEDY_FZ, 16, want_snr=False)
+    for l, H in enumerate(O.levels(16)):
+        v = ~np.isnan(hc[l])
+        np.testing.assert_allclose(hc[l][v], math.sqrt(H) * 1.5, rtol=1e-15)
+
+
+@pytest.mark.parametrize("z,delta,eps", [(5, 0.3, 0.45), (-7, 0.8, 0.3), (2, 0.05, 0.9),
+                                         (11, 0.5, 0.0)])
+def test_2d_greedy_fz_follows_a_comb_drifting_in_f_and_z(z, delta, eps):
+    """A signal whose H-th harmonic has fdot z + eps (away from zero) and whose
+    fundamental sits at m0 + delta puts harmonic k at column k m0 + floor(k delta)
+    and row round(k z / H) + sign(z) floor(k eps / ...) -- here written as the
+    offsets floor(k delta) and floor(k eps) that a 0/1-step path can follow.
+    On a background below every amplitude the drifting Greedy collects all of
+    them; Greedy along frequency alone loses those that left the rounded row."""
+    zmax, H, m0 = 24, 16, 150
+    nf = H * m0 + H + 2
+    s = (z > 0) - (z < 0)
+    rng = np.random.default_rng(abs(z))
+    x = rng.random((2 * zmax + 1, nf)) * 0.5
+    amps = [1.0 + 0.1 * k for k in range(1, H + 1)]
+
+    def rnd(k):
+        a = k * z
+        return (2 * a + H) // (2 * H) if a >= 0 else -((-2 * a + H) // (2 * H))
+
+    drifted = 0
+    for k in range(1, H + 1):
+        d = s * math.floor(k * eps)
+        drifted += d != 0
+        x[rnd(k) + d + zmax, k * m0 + math.floor(k * delta)] = amps[k - 1]
+    total = sum(amps)
+    assert O.sum_2d(x, zmax, O.GREEDY_FZ, H, m0, z) == pytest.approx(total, rel=1e-15)
+    # the mirror image at -z
+    assert O.sum_2d(x[::-1].copy(), zmax, O.GREEDY_FZ, H, m0, -z) == pytest.approx(total, rel=1e-15)
+    if drifted:
+        assert O.sum_2d(x, zmax, O.GREEDY, H, m0, z) < total - 0.5
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_2d_greedy_fz_is_one_of_its_paths(seed):
+    """On tiny planes of distinct integer bins every step path is enumerated
+    by brute force: the drifting Greedy's sum is one of the path sums and
+    never above their maximum. At level 2 its single step takes the largest of
+    the four candidates, two columns by two rows (fdot row away from zero)."""
+    zmax, H, nf = 3, 8, 40
+    rng = np.random.default_rng(100 + seed)
+    x = rng.permutation((2 * zmax + 1) * nf).reshape(2 * zmax + 1, nf).astype(np.float64)
+    for z in range(-zmax, zmax + 1):
+        for m in (1, 2, 3, 4):
+            got = O.sum_2d(x, zmax, O.GREEDY_FZ, H, m, z)
+            sums = _fz_paths(x, zmax, H, m, z)
+            assert got in sums, (z, m)
+            assert got <= max(sums)
+    for z in (-2, 2):
+        s = 1 if z > 0 else -1
+        m = 3
+        r1 = (z // abs(z)) * ((2 * abs(z) + 2) // 4) + zmax   # row of round(z / 2)
+        r2 = z + zmax                                         # row of round(2 z / 2)
+        cand = [x[r2, 2 * m], x[r2, 2 * m + 1], x[r2 + s, 2 * m], x[r2 + s, 2 * m + 1]]
+        assert O.sum_2d(x, zmax, O.GREEDY_FZ, 2, m, z) == x[r1, m] + max(cand)
+
+
+def test_2d_greedy_fz_constants_and_null_calibration():
+    # each later term is the largest of four exponentials
+    a4, v4 = order_stat_moments(4)
+    _, _, m64, q64 = O.snr_consts(O.GREEDY_FZ, 1.0, 1.0, 32)
+    for l, H in enumerate(O.levels(32)):
+        assert m64[l] == pytest.approx((1.0 + (H - 1) * a4) / math.sqrt(H), rel=1e-9)
+        assert 1.0 / q64[l] == pytest.approx(math.sqrt(1.0 + (H - 1) * v4) / math.sqrt(H), rel=1e-8)
+    # standardised noise: mean ~0, spread ~1 on drifting rows (fundamentals
+    # m >= H, rows whose paths stay inside the plane) and on the z = 0 row
+    zmax, nf, hmax = 40, 1 << 18, 16
+    x = np.stack([synth.exponential(77, r, nf) for r in range(2 * zmax + 1)]).astype(np.float64)
+    ms = np.arange(hmax, nf // hmax, 2, dtype=np.int64)
+    for z in (0, 9, -13):
+        fidx = ms
+        zidx = np.full(ms.size, z, np.int32)
+        h, mx, _, (m32, q32, m64, q64) = O.hrms_2d(x, zmax, O.GREEDY_FZ, hmax, fidx=fidx,
+                                                   zidx=zidx, f32=False)
+        nl = len(O.levels(hmax))
+        per = []
+        for l in range(nl):
+            c = nl + l if z == 0 else l
+            snr = (h[l] - m64[c]) * q64[c]
+            per.append(snr)
+            se = 1.0 / math.sqrt(ms.size)
+            assert abs(snr.mean()) < 6 * se + 0.01, (z, l, snr.mean())
+            assert abs(snr.std() - 1.0) < 0.04, (z, l, snr.std())
+        # the driver's maximum SNR uses the calibrated set of its row
+        assert np.array_equal(mx, np.max(np.stack(per), axis=0))
+
+
 def test_scale_f32():
     x = np.array([1.0, 3.0, 0.1, 65504.0], dtype=np.float32).astype(np.float64)
     # mu a power of two: exact scaling
