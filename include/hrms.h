@@ -75,6 +75,21 @@ typedef struct hrms_ctx* hrms_handle;
 
 enum { HRMS_EQ1 = 0, HRMS_MAX = 1, HRMS_FREQBIN = 2, HRMS_GREEDY = 3, HRMS_OPT = 4 };
 
+/* 2D only: Greedy with fdot drift. The paper names a Greedy sum on the
+ * frequency x fdot plane (abstract, Sec. 1) without defining it; read as
+ * eq. (4)'s step rule applied to the fdot row as well as to the column. With
+ * s = sign(z) and path offsets j (column), d (row, fdot units) starting at 0,
+ * output (m, z) of level H starts at the bin of harmonic 1; harmonic
+ * k = 2..H chooses among columns k m + j, k m + j + 1 of rows
+ * round(k z / H) + d and round(k z / H) + d + s (rows clamped to the plane),
+ * in that order, the first largest winning (strict >); j grows by one for the
+ * right column, d by s for the second row. At z = 0 this is HRMS_GREEDY along
+ * row 0. SNR constants: each later term is the largest of four bins, so
+ * m_H = H^-1/2 (mu + (H-1)(mu + 13/12 sigma)),
+ * 1/q_H = sigma H^-1/2 (1 + 205/144 (H-1))^1/2; the z = 0 row takes
+ * HRMS_GREEDY's. */
+enum { HRMS_GREEDY_FDOT = 5 };
+
 /* Storage type of the input bins. FP16 and BF16 widen exactly to FP32 before
  * any arithmetic. */
 enum { HRMS_F32 = 0, HRMS_F16 = 1, HRMS_BF16 = 2 };
@@ -172,7 +187,7 @@ typedef struct {
     int32_t nf;               /* frequency bins per row, 1 .. HRMS_MAX_BINS */
     int32_t zmax;             /* >= 0 */
     int32_t hmax;             /* power of two <= 32 */
-    int32_t variant;          /* HRMS_EQ1 .. HRMS_GREEDY */
+    int32_t variant;          /* HRMS_EQ1 .. HRMS_GREEDY, or HRMS_GREEDY_FDOT */
     int32_t dtype;
     uint32_t out_mask;
     int32_t stats_mode;
@@ -180,7 +195,9 @@ typedef struct {
     int64_t ld;               /* row stride in bins, >= nf */
     const void* x;            /* device: (2 zmax + 1) rows of ld bins, element-aligned */
     double* stats;            /* device: [2] = (mu, sigma) over the nf bins of every row */
-    float* snr_consts;        /* device or NULL: [HRMS_MAX_LEVELS][2] */
+    float* snr_consts;        /* device or NULL: [HRMS_MAX_LEVELS][2] = (m_H, q_H);
+                                 HRMS_GREEDY_FDOT: [2][HRMS_MAX_LEVELS][2], the
+                                 rows z != 0, then the row z = 0 */
     float* h;                 /* device: level H plane [2 zmax + 1][nf] (EQ1) or
                                  [2 zmax + 1][floor(nf / H)], packed level after
                                  level (hrms_layout_2d) */
@@ -274,7 +291,8 @@ int hrms_run_1d_noalloc(hrms_handle h, const hrms_run1d_args* a, void* hip_strea
 int hrms_autotune_1d(hrms_handle h, const hrms_run1d_args* a, void* hip_stream, int reps,
                      int32_t* chosen);
 
-/* Harmonic sum of a 2D plane, HRMS_EQ1 .. HRMS_GREEDY (HRMS_OPT: HRMS_E_UNSUPPORTED). */
+/* Harmonic sum of a 2D plane, HRMS_EQ1 .. HRMS_GREEDY and HRMS_GREEDY_FDOT
+ * (HRMS_OPT: HRMS_E_UNSUPPORTED). */
 int hrms_run_2d(hrms_handle h, const hrms_run2d_args* a, void* hip_stream);
 
 /* Normalise and store FP32 spectra as FP16 / BF16 (precision form of the 1D

@@ -238,6 +238,8 @@ int validate_1d(hrms_ctx* c, const hrms_run1d_args* a, bool device_ptrs)
 {
     if (!a) return fail(c, HRMS_E_INVAL, "args is NULL");
     if (a->n_spectra < 1) return fail(c, HRMS_E_INVAL, "n_spectra must be >= 1");
+    if (a->variant == HRMS_GREEDY_FDOT)
+        return fail(c, HRMS_E_UNSUPPORTED, "HRMS_GREEDY_FDOT drifts along fdot: 2D planes only");
     if (a->variant < HRMS_EQ1 || a->variant > HRMS_OPT)
         return fail(c, HRMS_E_INVAL, "variant must be HRMS_EQ1..HRMS_OPT");
     if (a->dtype < HRMS_F32 || a->dtype > HRMS_BF16)
@@ -300,8 +302,8 @@ int validate_2d(hrms_ctx* c, const hrms_run2d_args* a, bool device_ptrs)
         return fail(c, HRMS_E_INVAL, "hmax must be a power of two <= 32");
     if (a->variant == HRMS_OPT)
         return fail(c, HRMS_E_UNSUPPORTED, "HRMS_OPT is implemented for 1D spectra only");
-    if (a->variant < HRMS_EQ1 || a->variant > HRMS_GREEDY)
-        return fail(c, HRMS_E_INVAL, "variant must be HRMS_EQ1..HRMS_GREEDY");
+    if (a->variant < HRMS_EQ1 || a->variant > HRMS_GREEDY_FDOT)
+        return fail(c, HRMS_E_INVAL, "variant must be HRMS_EQ1..HRMS_GREEDY or HRMS_GREEDY_FDOT");
     if (a->dtype < HRMS_F32 || a->dtype > HRMS_BF16)
         return fail(c, HRMS_E_INVAL, "dtype must be HRMS_F32, HRMS_F16 or HRMS_BF16");
     if (a->out_mask & ~7u) return fail(c, HRMS_E_INVAL, "out_mask has unknown bits");
@@ -694,7 +696,8 @@ int get_plan_2d(hrms_ctx* c, const hrms_run2d_args* a, hipStream_t stream, Plan2
     if ((e = upload(P->d_plane, P->plane, stream)) != hipSuccess) return hip_fail(c, e, "upload plane");
     if ((e = P->d_partial.ensure(P->segs.size() * 2 * sizeof(double))) != hipSuccess)
         return hip_fail(c, e, "alloc partials");
-    if ((e = P->d_consts.ensure(kMaxLevels * sizeof(LevelConst))) != hipSuccess)
+    // two sets: Greedy with fdot drift keeps eq. (4)'s for its z = 0 row
+    if ((e = P->d_consts.ensure(2 * kMaxLevels * sizeof(LevelConst))) != hipSuccess)
         return hip_fail(c, e, "alloc consts");
     *out = P;
     return HRMS_OK;
@@ -1364,6 +1367,15 @@ int hrms_run_2d(hrms_handle h, const hrms_run2d_args* a, void* hip_stream)
     cp.variant = a->variant;
     cp.compute_stats = compute ? 1 : 0;
     if ((e = launch_consts(cp, stream)) != hipSuccess) return hip_fail(h, e, "constants launch");
+    if (a->variant == HRMS_GREEDY_FDOT) {
+        // the z = 0 row: eq. (4)'s constants, from the statistics just written
+        cp.consts = (LevelConst*)P->d_consts.p + kMaxLevels;
+        cp.user_consts = a->snr_consts ? a->snr_consts + 2 * HRMS_MAX_LEVELS : nullptr;
+        cp.variant = HRMS_GREEDY;
+        cp.compute_stats = 0;
+        if ((e = launch_consts(cp, stream)) != hipSuccess)
+            return hip_fail(h, e, "constants launch");
+    }
     if (a->out_mask != 0) {
         Run2DParams rp{};
         rp.x = a->x;

@@ -36,6 +36,8 @@ namespace hrms {
 namespace {
 
 constexpr int kEq1 = 0, kMax = 1, kFreqbin = 2, kGreedy = 3, kOpt = 4;
+// 2D only: Greedy with fdot drift (eq. (4)'s step rule on the fdot row as well)
+constexpr int kGreedyFZ = 5;
 constexpr int kF32 = 0, kF16 = 1, kBF16 = 2;
 
 template <int DT>
@@ -1020,6 +1022,12 @@ __device__ void level_consts(int variant, double mu, double sigma, int H, double
         }
         mean_s = sum_mean;
         var_s = (sigma * sigma) * sum_psi;
+    } else if (variant == kGreedyFZ) {
+        // Greedy with fdot drift: one bin, then H - 1 maxima of four fresh
+        // bins (two rows by two columns): mean mu + 13/12 sigma, variance
+        // Psi_4 sigma^2 = 205/144 sigma^2
+        mean_s = mu + (double)(H - 1) * (mu + (13.0 / 12.0) * sigma);
+        var_s = (sigma * sigma) * (1.0 + (205.0 / 144.0) * (double)(H - 1));
     } else {
         // Greedy: one bin, then H - 1 maxima of two fresh bins
         mean_s = mu + (double)(H - 1) * (mu + 0.5 * sigma);
@@ -1411,7 +1419,10 @@ __global__ __launch_bounds__(WG) void k_hrms1d_win(const Run1DParams p)
 // round(i z / H) (halves away from zero), and along that row the 1D form of
 // the variant: column round(i f / H) (eq. (1), halves up), the window
 // i f .. i f + i - 1 (eq. (2)), column i f (eq. (3)) or i f + j (eq. (4), j as
-// there). Each level is summed on its own, in the order i = 1..H. A thread owns
+// there). Greedy with fdot drift also lets the row move: harmonic k chooses
+// among columns k f + j, k f + j + 1 of rows round(k z / H) + d and that row
+// plus sign(z) (clamped to the plane), the first largest winning, and j, d
+// follow the choice. Each level is summed on its own, in the order i = 1..H. A thread owns
 // one output; a workgroup holds 64 consecutive frequencies of kZRows fdot rows,
 // the rows being the fastest grid dimension so that neighbouring workgroups
 // read the same columns.
@@ -1498,6 +1509,36 @@ __global__ __launch_bounds__(64 * kZRows) void k_hrms2d(const Run2DParams p)
                         acc = acc + buffer_elem<DT>(rs, i * m);
                     }
                 }
+            } else if constexpr (VAR == kGreedyFZ) {
+                // the path's row offset d differs from lane to lane, so rows
+                // are addressed per lane; rows are clamped to the plane
+                const int sg = z > 0 ? 1 : (z < 0 ? -1 : 0);
+                acc = load_scalar<DT>(p.x, (int64_t)(row_of(z, l) + p.zmax) * p.ld + m);
+                int j = 0, d = 0;
+#pragma unroll
+                for (int k = 2; k <= (1 << (kMaxLevels - 1)); ++k) {
+                    if (k <= H) {
+                        const int rk = row_of(k * z, l);
+                        const int r0 = min(max(rk + d, -p.zmax), p.zmax) + p.zmax;
+                        const int r1 = min(max(rk + d + sg, -p.zmax), p.zmax) + p.zmax;
+                        const int64_t c = (int64_t)k * m + j;
+                        const int64_t b0 = (int64_t)r0 * p.ld + c;
+                        const int64_t b1 = (int64_t)r1 * p.ld + c;
+                        const float x00 = load_scalar<DT>(p.x, b0);
+                        const float x01 = load_scalar<DT>(p.x, b0 + 1);
+                        const float x10 = load_scalar<DT>(p.x, b1);
+                        const float x11 = load_scalar<DT>(p.x, b1 + 1);
+                        // the first largest in the order x00, x01, x10, x11
+                        float v = x00;
+                        int pick = 0;
+                        if (x01 > v) { v = x01; pick = 1; }
+                        if (x10 > v) { v = x10; pick = 2; }
+                        if (x11 > v) { v = x11; pick = 3; }
+                        acc = acc + v;
+                        j += pick & 1;
+                        d += (pick & 2) ? sg : 0;
+                    }
+                }
             } else {
                 acc = buffer_elem<DT>(plane_row<DT>(p, row_of(z, l) + p.zmax), m);
                 int j = 0;
@@ -1517,7 +1558,9 @@ __global__ __launch_bounds__(64 * kZRows) void k_hrms2d(const Run2DParams p)
                     }
                 }
             }
-            const LevelConst c = p.consts[l];
+            // Greedy with fdot drift: the z = 0 row cannot drift and has
+            // eq. (4)'s constants, the second set
+            const LevelConst c = p.consts[(VAR == kGreedyFZ && z == 0) ? kMaxLevels + l : l];
             const float hv = acc * c.rh;
             const int plane = VAR == kEq1 ? p.nf : (p.nf >> l);
             if (p.out_mask & 1u)
@@ -1853,6 +1896,7 @@ hipError_t launch_hrms2d(int variant, int dtype, const Run2DParams& p, hipStream
     case kMax: k = kernel_2d<kMax>(dtype); break;
     case kFreqbin: k = kernel_2d<kFreqbin>(dtype); break;
     case kGreedy: k = kernel_2d<kGreedy>(dtype); break;
+    case kGreedyFZ: k = kernel_2d<kGreedyFZ>(dtype); break;
     default: return hipErrorInvalidValue;
     }
     hipLaunchKernelGGL(k, grid, block, 0, s, p);

@@ -19,6 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhrms.so")
 
 HRMS_EQ1, HRMS_MAX, HRMS_FREQBIN, HRMS_GREEDY, HRMS_OPT = 0, 1, 2, 3, 4
+HRMS_GREEDY_FDOT = 5   # 2D only
 HRMS_F32, HRMS_F16, HRMS_BF16 = 0, 1, 2
 HRMS_OUT_H, HRMS_OUT_MAXSNR, HRMS_OUT_BESTH, HRMS_OUT_CAND, HRMS_OUT_PEAKS = 1, 2, 4, 8, 16
 HRMS_OUT_ALL = 7
@@ -29,7 +30,7 @@ HRMS_MAX_LEVELS = 6
 HRMS_MAX_BINS = 1 << 26
 
 VARIANTS = {"eq1": HRMS_EQ1, "max": HRMS_MAX, "freqbin": HRMS_FREQBIN, "greedy": HRMS_GREEDY,
-            "opt": HRMS_OPT}
+            "opt": HRMS_OPT, "greedy_fdot": HRMS_GREEDY_FDOT}
 DTYPES = {"f32": HRMS_F32, "f16": HRMS_F16, "bf16": HRMS_BF16}
 
 EXPORTED = ["hrms_create", "hrms_destroy", "hrms_layout_1d", "hrms_layout_2d", "hrms_run_1d",

@@ -16,7 +16,7 @@ import numpy as np
 from oracle import oracle as O
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-NAMES = {0: "eq1", 1: "max", 2: "freqbin", 3: "greedy", 4: "opt"}
+NAMES = {0: "eq1", 1: "max", 2: "freqbin", 3: "greedy", 4: "opt", 5: "greedy_fdot"}
 # FP32 relative error bound of the sums against the binary64 oracle
 REL_TOL_F64 = 1e-5
 

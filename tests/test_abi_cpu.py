@@ -95,7 +95,7 @@ def layout_status(a):
     (dict(offsets=[0, 10], hmax_all=64), "Hmax"),
     (dict(offsets=[0, 10], hmax_all=0), "Hmax"),
     (dict(offsets=[0, 10, 20], hmax=[8, 12]), "spectrum 1"),
-    (dict(offsets=[0, 10], variant=5), "variant"),
+    (dict(offsets=[0, 10], variant=6), "variant"),
     (dict(offsets=[0, 10], dtype=3), "dtype"),
     (dict(offsets=[0, 10], out_mask=32), "out_mask"),
     (dict(offsets=[0, 10], out_mask=16 | 1), "HRMS_OUT_MAXSNR"),
@@ -155,7 +155,7 @@ def test_layout_2d_and_invalid_planes(variant):
     a.reserved = 1
     assert H.lib().hrms_layout_2d(C.byref(a), None, None) == H.HRMS_E_INVAL
     a.reserved = 0
-    a.variant = 5
+    a.variant = 6
     assert H.lib().hrms_layout_2d(C.byref(a), None, None) == H.HRMS_E_INVAL
 
 
@@ -178,6 +178,19 @@ def test_exhaustive_path_sum_is_h_only_and_1d_only():
     a = H.hrms_run2d_args()
     a.nf, a.zmax, a.hmax, a.variant, a.ld, a.out_mask = 1000, 3, 16, H.HRMS_OPT, 1000, 1
     assert H.lib().hrms_layout_2d(C.byref(a), None, None) == H.HRMS_E_UNSUPPORTED
+
+
+def test_fdot_drifting_greedy_is_2d_only():
+    a = make_args([0, 100], variant=H.HRMS_GREEDY_FDOT)
+    assert layout_status(a)[0] == H.HRMS_E_UNSUPPORTED
+    assert "2D" in H.last_error(None)
+    p = H.hrms_run2d_args()
+    p.nf, p.zmax, p.hmax, p.variant, p.ld, p.out_mask = 1000, 3, 16, H.HRMS_GREEDY_FDOT, 1000, 7
+    offs, total = H.hrms_layout_2d(p)
+    # compact planes as for eq. (2)-(4): 7 rows of floor(1000 / H) per level
+    assert list(offs[:5]) == [0, 7000, 10500, 12250, 13125] and total == 7 * (1000 + 500 + 250 + 125 + 62)
+    p.variant = 6
+    assert H.lib().hrms_layout_2d(C.byref(p), None, None) == H.HRMS_E_INVAL
 
 
 def test_binding_rejects_host_short_or_strided_inputs():

@@ -17,6 +17,9 @@ from tests.gpu_helpers import NAMES, REL_TOL_F64, case_log
 
 pytestmark = pytest.mark.gpu
 
+# eq. (1)-(4) along frequency, and Greedy with fdot drift
+VARIANTS_2D = [O.EQ1, O.MAX, O.FREQBIN, O.GREEDY, O.GREEDY_FZ]
+
 
 @pytest.fixture(scope="module")
 def handle():
@@ -45,7 +48,8 @@ def run_2d_device(handle, plane_dev, nf, zmax, hmax, variant, ld=None, stats=Non
     dev = plane_dev.device
     st = stats if stats is not None else torch.zeros(2, dtype=torch.float64, device=dev)
     a.stats_mode = 1 if stats is not None else 0
-    consts = torch.zeros((6, 2), dtype=torch.float32, device=dev)
+    # two sets of level constants: Greedy with fdot drift keeps eq. (4)'s for z = 0
+    consts = torch.zeros((12, 2), dtype=torch.float32, device=dev)
     h = torch.empty(max(total, 1), dtype=torch.float32, device=dev)
     ms = torch.empty(rows * nf, dtype=torch.float32, device=dev)
     bh = torch.empty(rows * nf, dtype=torch.uint8, device=dev)
@@ -70,6 +74,10 @@ def check_plane(out, seen, nf, zmax, hmax, variant, fidx=None, zidx=None, stats=
         mu, sd = stats
     m32, q32, _, _ = O.snr_consts(variant, mu, sd, hmax)
     assert np.array_equal(out["consts"][:nl, 0], m32) and np.array_equal(out["consts"][:nl, 1], q32)
+    if variant == O.GREEDY_FZ:
+        g32, gq32, _, _ = O.snr_consts(O.GREEDY, mu, sd, hmax)
+        assert np.array_equal(out["consts"][6:6 + nl, 0], g32)
+        assert np.array_equal(out["consts"][6:6 + nl, 1], gq32)
     h32, ms32, bh32, _ = O.hrms_2d(seen, zmax, variant, hmax, fidx=fidx, zidx=zidx, f32=True,
                                     mu=mu, sigma=sd)
     if fidx is None:
@@ -107,7 +115,7 @@ def to_dev(x2d, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
-@pytest.mark.parametrize("variant", [O.EQ1, O.MAX, O.FREQBIN, O.GREEDY])
+@pytest.mark.parametrize("variant", VARIANTS_2D)
 def test_small_plane_every_output(handle, variant, dtype):
     zmax, nf = 7, 20003
     x, _ = synth.plane(nf=nf, zmax=zmax, seed=55, n_comb=4, f0_max=nf // 20)
@@ -118,7 +126,7 @@ def test_small_plane_every_output(handle, variant, dtype):
                 label=f"2d-{dtype}")
 
 
-@pytest.mark.parametrize("variant", [O.EQ1, O.MAX, O.FREQBIN, O.GREEDY])
+@pytest.mark.parametrize("variant", VARIANTS_2D)
 def test_plane_with_row_padding_and_provided_stats(handle, variant):
     import torch
     zmax, nf, ld = 3, 5001, 5008
@@ -133,7 +141,7 @@ def test_plane_with_row_padding_and_provided_stats(handle, variant):
     check_plane(out, seen, nf, zmax, 32, variant, stats=(1.1, 0.9), label="2d-ld")
 
 
-@pytest.mark.parametrize("variant", [O.EQ1, O.MAX, O.FREQBIN, O.GREEDY])
+@pytest.mark.parametrize("variant", VARIANTS_2D)
 def test_fdot_plane_full_size_sampled(handle, variant):
     """85 fdot rows x 2^21 frequency bins, Hmax = 16, 20 accelerated combs;
     sampled outputs against the oracle, plus recovery of the on-bin combs at
@@ -168,13 +176,13 @@ def test_variants_alternate_on_one_handle(handle):
     zmax, nf = 2, 3001
     x, _ = synth.plane(nf=nf, zmax=zmax, seed=57, n_comb=2, f0_max=150)
     xd, seen = to_dev(x, "f32")
-    for variant in (O.EQ1, O.MAX, O.EQ1, O.GREEDY, O.FREQBIN, O.EQ1):
+    for variant in (O.EQ1, O.MAX, O.EQ1, O.GREEDY, O.GREEDY_FZ, O.FREQBIN, O.EQ1):
         case_log(f"2d alternating variants: {NAMES[variant]}")
         out = run_2d(handle, xd, nf, zmax, 8, variant)
         check_plane(out, seen, nf, zmax, 8, variant, label=f"alt-{NAMES[variant]}")
 
 
-@pytest.mark.parametrize("variant", [O.EQ1, O.MAX, O.FREQBIN, O.GREEDY])
+@pytest.mark.parametrize("variant", VARIANTS_2D)
 def test_maximum_length_rows_sampled(handle, variant):
     """Rows of the largest length the library accepts (2^26 frequency bins),
     3 fdot rows, Hmax = 16; sampled outputs, including the last bins of every
