@@ -28,7 +28,10 @@ The JSON line also carries:
 
 --workload uneven: 512 spectra of log-uniform length 2^14..2^23 with Hmax in
 {8, 16, 32}: one graph-captured persistent launch vs per-spectrum launches.
---workload plane: 85 fdot rows x 2^21 bins, Hmax = 16, all four variants.
+--workload plane: 85 fdot rows x 2^21 bins, Hmax = 16, all four variants and
+Greedy with fdot drift, FP32 and FP16 storage.
+The default workload also runs the other two and reports them under "plane"
+and "uneven" (--no-sub skips them).
 """
 from __future__ import annotations
 
@@ -68,6 +71,8 @@ def parse():
     ap.add_argument("--cpu-baseline-spectra", type=int, default=400,
                     help="spectra in the oracle's timed sample (0 skips it)")
     ap.add_argument("--cpu-threads", type=int, default=0, help="0: min(16, cores)")
+    ap.add_argument("--no-sub", action="store_true",
+                    help="with the default workload, skip the plane and uneven-batch sub-results")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after timing, copy the input once (a dispatch of known bytes for "
                          "scaling the FETCH_SIZE / WRITE_SIZE counters)")
@@ -603,40 +608,70 @@ def workload_plane(args):
     xd = torch.from_numpy(x).cuda()
     rows = 2 * zmax + 1
     handle = H.hrms_create(0)
-    res = {}
-    for v in (H.HRMS_EQ1, H.HRMS_MAX, H.HRMS_FREQBIN, H.HRMS_GREEDY):
-        a = H.hrms_run2d_args()
-        a.nf, a.zmax, a.hmax, a.variant, a.ld, a.out_mask = nf, zmax, hmax, v, nf, 7
-        offs, tot = H.hrms_layout_2d(a)
-        st = torch.zeros(2, dtype=torch.float64, device="cuda")
-        hb = torch.empty(tot, dtype=torch.float32, device="cuda")
-        ms = torch.empty(rows * nf, dtype=torch.float32, device="cuda")
-        bh = torch.empty(rows * nf, dtype=torch.uint8, device="cuda")
-        a.x, a.stats, a.h, a.max_snr, a.best_h = (xd.data_ptr(), st.data_ptr(), hb.data_ptr(),
-                                                  ms.data_ptr(), bh.data_ptr())
-        stream = torch.cuda.current_stream()
-        for _ in range(args.warmup):
-            H.hrms_run_2d(handle, a, stream)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(args.steps):
-            H.hrms_run_2d(handle, a, stream)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        t = e0.elapsed_time(e1) / args.steps
-        byts = rows * nf * 4 + 4 * tot + 5 * rows * nf
-        res[VARIANT_NAMES[v]] = {"ms": round(t, 4), "gbins_per_s": round(rows * nf / t / 1e6, 2),
-                                 "alg_bytes": byts, "frac_hbm": round(byts / t / 1e9 / 8.0, 4)}
-    H.hrms_destroy(handle)
+    names = {H.HRMS_EQ1: "eq1", H.HRMS_MAX: "max", H.HRMS_FREQBIN: "freqbin",
+             H.HRMS_GREEDY: "greedy", H.HRMS_GREEDY_FDOT: "greedy_fdot"}
+
+    def timed(plane, dtype_code, stats=None):
+        res = {}
+        for v in names:
+            a = H.hrms_run2d_args()
+            a.nf, a.zmax, a.hmax, a.variant, a.ld, a.out_mask = nf, zmax, hmax, v, nf, 7
+            a.dtype = dtype_code
+            offs, tot = H.hrms_layout_2d(a)
+            st = stats if stats is not None else torch.zeros(2, dtype=torch.float64,
+                                                             device="cuda")
+            a.stats_mode = H.HRMS_STATS_PROVIDED if stats is not None else H.HRMS_STATS_COMPUTE
+            hb = torch.empty(tot, dtype=torch.float32, device="cuda")
+            ms = torch.empty(rows * nf, dtype=torch.float32, device="cuda")
+            bh = torch.empty(rows * nf, dtype=torch.uint8, device="cuda")
+            a.x, a.stats, a.h, a.max_snr, a.best_h = (plane.data_ptr(), st.data_ptr(),
+                                                      hb.data_ptr(), ms.data_ptr(), bh.data_ptr())
+            stream = torch.cuda.current_stream()
+            for _ in range(args.warmup):
+                H.hrms_run_2d(handle, a, stream)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(args.steps):
+                H.hrms_run_2d(handle, a, stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1) / args.steps
+            byts = rows * nf * plane.element_size() + 4 * tot + 5 * rows * nf
+            res[names[v]] = {"ms": round(t, 4), "gbins_per_s": round(rows * nf / t / 1e6, 2),
+                             "alg_bytes": byts, "frac_hbm": round(byts / t / 1e9 / 8.0, 4)}
+            del hb, ms, bh
+        return res
+
+    res = timed(xd, H.HRMS_F32)
     tot_ms = sum(r["ms"] for r in res.values())
+    # precision form: the plane normalised to unit mean and stored as FP16
+    # (one spectrum of rows x nf bins), statistics (1, sigma / mu) provided
+    off = np.array([0, rows * nf], np.int64)
+    y = torch.empty(rows * nf, dtype=torch.float16, device="cuda")
+    st_raw = torch.zeros((1, 2), dtype=torch.float64, device="cuda")
+    st_out = torch.zeros((1, 2), dtype=torch.float64, device="cuda")
+    qa = H.hrms_quantize_args()
+    qa.n_spectra, qa.dtype, qa.stats_mode = 1, H.HRMS_F16, H.HRMS_STATS_COMPUTE
+    qa.x, qa.offsets, qa.stats, qa.stats_out, qa.y = (xd.data_ptr(), off.ctypes.data,
+                                                       st_raw.data_ptr(), st_out.data_ptr(),
+                                                       y.data_ptr())
+    H.hrms_quantize(handle, qa)
+    torch.cuda.synchronize()
+    res16 = timed(y, H.HRMS_F16, stats=st_out.reshape(2))
+    tot16 = sum(r["ms"] for r in res16.values())
+    H.hrms_destroy(handle)
     return {"metric": METRIC, "value": round(rows * nf / tot_ms / 1e6, 3),
             "unit": "G input bins/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": round(tot_ms, 4), "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "2D f-fdot plane 85 x 2^21 FP32, 20 accelerated combs, "
-                                   "Hmax=16, eq. (1), Max, freq-bin, Greedy (stats included)"},
-            "per_variant": res}
+                                   "Hmax=16, eq. (1), Max, freq-bin, Greedy, Greedy with fdot "
+                                   "drift (statistics included)"},
+            "per_variant": res,
+            "fp16_storage": {"value": round(rows * nf / tot16 / 1e6, 3), "unit": "G input bins/s",
+                             "ms_per_step": round(tot16, 4), "per_variant": res16,
+                             "speedup_vs_fp32": round(tot_ms / tot16, 3)}}
 
 
 def main():
@@ -648,6 +683,18 @@ def main():
         sys.exit(2)
     fn = {"batch": workload_batch, "uneven": workload_uneven, "plane": workload_plane}
     out = fn[args.workload](args)
+    if args.workload == "batch" and not args.no_sub:
+        # the other two workloads, reported beside the 1D batch's line
+        import torch
+        torch.cuda.empty_cache()
+        for name in ("plane", "uneven"):
+            sub = fn[name](args)
+            out[name] = {k: sub[k] for k in ("value", "unit", "ms_per_step", "config",
+                                             "per_variant") if k in sub}
+            for k in ("fp16_storage",):
+                if k in sub:
+                    out[name][k] = sub[k]
+            torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
 
 

@@ -61,6 +61,18 @@
  *   - Every argument is checked before anything is enqueued. On error nothing
  *     is enqueued, no output is touched and a negative status is returned;
  *     hrms_last_error() gives the reason. No call aborts or throws.
+ *
+ * Environment (read by hrms_create)
+ *   HRMS_NO_GRAPH=1        enqueue launches directly instead of replaying graphs
+ *   HRMS_LOG=1             one line on stderr per plan built, graph captured,
+ *                          tune cache read, no-alloc table copy and error
+ *   HRMS_FAULT_INJECT=...  comma-separated injected failures for testing error
+ *                          paths: "alloc" fails every device allocation of the
+ *                          library (HRMS_E_NOMEM, nothing enqueued), "launch"
+ *                          fails the harmonic-sum launch of every call
+ *                          (HRMS_E_HIP; the statistics and constants launches
+ *                          before it may have been enqueued); the handle stays
+ *                          usable and destroyable
  */
 #ifndef HRMS_H
 #define HRMS_H

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -34,6 +35,31 @@ constexpr int kStatsSeg = 1 << 16;   // bins per statistics segment
 constexpr int kPlanCache = 4;
 
 thread_local std::string g_last_error;
+
+// Injected failures (environment HRMS_FAULT_INJECT, a comma-separated list read
+// by hrms_create) for testing callers' error paths: "alloc" makes every device
+// allocation of the library fail (HRMS_E_NOMEM, before anything is enqueued),
+// "launch" the harmonic-sum launch of every call (HRMS_E_HIP, after the
+// statistics and constants launches were enqueued). The handle stays usable
+// and destroyable; hrms_run_1d_noalloc allocates nothing, so "alloc" leaves
+// it working.
+constexpr unsigned kFaultAlloc = 1u, kFaultLaunch = 2u;
+
+unsigned parse_faults(const char* s)
+{
+    unsigned f = 0;
+    if (!s) return 0;
+    const std::string v(s);
+    size_t pos = 0;
+    while (pos <= v.size()) {
+        const size_t end = std::min(v.find(',', pos), v.size());
+        const std::string tok = v.substr(pos, end - pos);
+        if (tok == "alloc") f |= kFaultAlloc;
+        if (tok == "launch") f |= kFaultLaunch;
+        pos = end + 1;
+    }
+    return f;
+}
 
 struct DeviceBuf {
     void* p = nullptr;
@@ -193,6 +219,8 @@ struct hrms_ctx {
     std::map<TuneKey, Shape1D> tune;
     hipStream_t capture = nullptr;   // private stream for graph capture
     bool graphs = true;
+    bool log = false;                // HRMS_LOG: one line per plan, capture and error on stderr
+    unsigned fault = 0;              // HRMS_FAULT_INJECT: kFaultAlloc | kFaultLaunch
     std::vector<std::unique_ptr<Plan1D>> plans;   // most recent last
     // host-only plans of hrms_run_1d_noalloc (their tables live in the
     // device's static scratch), most recent last
@@ -205,13 +233,34 @@ struct hrms_ctx {
 
 namespace {
 
+void hlog(const hrms_ctx* c, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+void hlog(const hrms_ctx* c, const char* fmt, ...)
+{
+    if (!c || !c->log) return;
+    std::va_list ap;
+    va_start(ap, fmt);
+    std::fprintf(stderr, "[hrms] ");
+    std::vfprintf(stderr, fmt, ap);
+    std::fprintf(stderr, "\n");
+    va_end(ap);
+}
+
 int fail(hrms_ctx* c, int status, const std::string& msg)
 {
-    if (c)
+    if (c) {
         c->err = msg;
-    else
+        hlog(c, "error %d: %s", status, msg.c_str());
+    } else {
         g_last_error = msg;
+    }
     return status;
+}
+
+// An injected allocation failure, checked before a call allocates.
+int alloc_fault(hrms_ctx* c)
+{
+    if (!(c->fault & kFaultAlloc)) return HRMS_OK;
+    return fail(c, HRMS_E_NOMEM, "injected allocation failure (HRMS_FAULT_INJECT=alloc)");
 }
 
 int hip_fail(hrms_ctx* c, hipError_t e, const char* what)
@@ -620,6 +669,7 @@ int upload_plan_1d(hrms_ctx* c, Plan1D* P, hipStream_t stream)
 {
     const int ns = (int)P->spec.size();
     hipError_t e;
+    if (int f = alloc_fault(c)) return f;
     if ((e = upload(P->d_spec, P->spec, stream)) != hipSuccess) return hip_fail(c, e, "upload spec");
     if ((e = upload(P->d_tiles, P->tiles, stream)) != hipSuccess)
         return hip_fail(c, e, "upload tiles");
@@ -665,6 +715,7 @@ int get_plan_2d(hrms_ctx* c, const hrms_run2d_args* a, hipStream_t stream, Plan2
         *out = P;
         return HRMS_OK;
     }
+    if (int f = alloc_fault(c)) return f;
     // (the old plan waits for its last use before its buffers are freed)
     c->plan2d.reset(new (std::nothrow) Plan2D());
     P = c->plan2d.get();
@@ -712,6 +763,7 @@ int get_plan_q(hrms_ctx* c, const hrms_quantize_args* a, hipStream_t stream, Pla
         *out = P;
         return HRMS_OK;
     }
+    if (int f = alloc_fault(c)) return f;
     c->planq.reset(new (std::nothrow) PlanQ());
     P = c->planq.get();
     if (!P) return fail(c, HRMS_E_NOMEM, "host allocation failed");
@@ -796,6 +848,14 @@ bool same_signature(const Plan1D& P, const hrms_run1d_args* a, const Shape1D& sh
     return true;
 }
 
+void log_plan(const hrms_ctx* c, const Plan1D& P, const char* what)
+{
+    hlog(c, "%s: %zu spectra, variant %d, dtype %d, shape %dx%d chunk %d top %d; %zu + %zu tiles "
+            "in %d queues, grids %d + %d",
+         what, P.spec.size(), P.variant, P.dtype, P.shape.wg, P.shape.r, P.shape.chunk,
+         P.shape.top, P.tiles.size(), P.tiles_top.size(), P.nqueues, P.grid, P.grid_top);
+}
+
 int get_plan_1d(hrms_ctx* c, const hrms_run1d_args* a, const Shape1D& shape, hipStream_t stream,
                 Plan1D** out)
 {
@@ -813,6 +873,7 @@ int get_plan_1d(hrms_ctx* c, const hrms_run1d_args* a, const Shape1D& shape, hip
     int st = plan_host_1d(c, a, shape, p.get());
     if (st == HRMS_OK) st = upload_plan_1d(c, p.get(), stream);
     if (st != HRMS_OK) return st;
+    log_plan(c, *p, "plan");
     if ((int)c->plans.size() >= kPlanCache) {
         // the evicted plan waits for its last use before its buffers are freed
         c->plans.erase(c->plans.begin());
@@ -872,7 +933,10 @@ void load_tune(hrms_ctx* c)
                                   &k.lenlog, &sh.wg, &sh.r, &sh.chunk, &sh.top)) == 8) {
             if (hrms1d_shape_supported(k.variant, sh)) t[k] = sh;
         }
-        if (got == EOF) c->tune.swap(t);
+        if (got == EOF) {
+            c->tune.swap(t);
+            hlog(c, "tune cache %s: %zu batch classes", c->tune_path.c_str(), c->tune.size());
+        }
     }
     std::fclose(f);
 }
@@ -916,7 +980,7 @@ PlanDev plan_dev(const Plan1D& P)
 
 // Enqueues statistics (or not), constants and the harmonic sum.
 hipError_t enqueue_1d(const hrms_run1d_args* a, const Plan1D* P, const PlanDev& D,
-                      const Shape1D& shape, hipStream_t stream)
+                      const Shape1D& shape, hipStream_t stream, bool fail_launch)
 {
     hipError_t e;
     const bool compute = a->stats_mode == HRMS_STATS_COMPUTE;
@@ -955,6 +1019,7 @@ hipError_t enqueue_1d(const hrms_run1d_args* a, const Plan1D* P, const PlanDev& 
         rp.cand_count = a->cand_count;
         rp.cand_cap = a->cand_capacity;
         rp.cand_thr = a->cand_threshold;
+        if (fail_launch) return hipErrorLaunchFailure;   // injected (HRMS_FAULT_INJECT=launch)
         if (!P->tiles.empty() &&
             (e = launch_hrms1d(a->variant, a->dtype, shape, rp, P->grid, stream)) != hipSuccess)
             return e;
@@ -995,7 +1060,7 @@ int run_1d_with(hrms_ctx* h, const hrms_run1d_args* a, hipStream_t stream, const
     if ((e = P->order.before(stream)) != hipSuccess) return hip_fail(h, e, "stream ordering");
     if (!graphs) {
         UseGuard use(P->order, stream);
-        if ((e = enqueue_1d(a, P, plan_dev(*P), shape, stream)) != hipSuccess)
+        if ((e = enqueue_1d(a, P, plan_dev(*P), shape, stream, (h->fault & kFaultLaunch) != 0)) != hipSuccess)
             return hip_fail(h, e, "launch");
         if ((e = use.finish()) != hipSuccess) return hip_fail(h, e, "hipEventRecord");
         return HRMS_OK;
@@ -1017,7 +1082,7 @@ int run_1d_with(hrms_ctx* h, const hrms_run1d_args* a, hipStream_t stream, const
         }
         if ((e = hipStreamBeginCapture(h->capture, hipStreamCaptureModeThreadLocal)) != hipSuccess)
             return hip_fail(h, e, "hipStreamBeginCapture");
-        const hipError_t le = enqueue_1d(a, P, plan_dev(*P), shape, h->capture);
+        const hipError_t le = enqueue_1d(a, P, plan_dev(*P), shape, h->capture, (h->fault & kFaultLaunch) != 0);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(h->capture, &g);
         if (le != hipSuccess || e != hipSuccess) {
@@ -1031,6 +1096,7 @@ int run_1d_with(hrms_ctx* h, const hrms_run1d_args* a, hipStream_t stream, const
             return hip_fail(h, e, "hipGraphInstantiate");
         }
         P->gkey = key;
+        hlog(h, "graph captured: variant %d, %zu spectra", P->variant, P->spec.size());
     }
     if ((e = hipGraphLaunch(P->gexec, stream)) != hipSuccess) return hip_fail(h, e, "hipGraphLaunch");
     if ((e = P->order.after(stream)) != hipSuccess) return hip_fail(h, e, "hipEventRecord");
@@ -1105,6 +1171,7 @@ int get_plan_1d_host(hrms_ctx* c, const hrms_run1d_args* a, const Shape1D& shape
     const int st = plan_host_1d(c, a, shape, p.get());
     if (st != HRMS_OK) return st;
     p->serial = ++g_plan_serial;
+    log_plan(c, *p, "no-alloc plan");
     if ((int)c->na_plans.size() >= kPlanCache) {
         // the evicted plan's host tables may still be the source of a queued
         // copy: the device finishes its work before they are freed
@@ -1151,13 +1218,15 @@ int run_1d_noalloc(hrms_ctx* h, const hrms_run1d_args* a, hipStream_t stream)
                 (e = copy_section(base, L.tiles, P->tiles, stream)) == hipSuccess &&
                 (e = copy_section(base, L.tiles_top, P->tiles_top, stream)) == hipSuccess &&
                 (e = copy_section(base, L.segs, P->segs, stream)) == hipSuccess &&
-                (e = copy_section(base, L.seg_first, P->seg_first, stream)) == hipSuccess)
+                (e = copy_section(base, L.seg_first, P->seg_first, stream)) == hipSuccess) {
                 owner = P->serial;
+                hlog(h, "no-alloc tables copied: %zu bytes of scratch", L.total);
+            }
         }
     }
     if (e != hipSuccess) return hip_fail(h, e, "copying the plan into the static scratch");
     // the queue counters and the candidate count are cleared by the constants kernel
-    if ((e = enqueue_1d(a, P, plan_dev_at(base, L), shape, stream)) != hipSuccess)
+    if ((e = enqueue_1d(a, P, plan_dev_at(base, L), shape, stream, (h->fault & kFaultLaunch) != 0)) != hipSuccess)
         return hip_fail(h, e, "launch");
     return HRMS_OK;
 }
@@ -1210,6 +1279,8 @@ int hrms_create(hrms_handle* out, int device_ordinal, const char* tune_cache_pat
     c->cu_count = prop.multiProcessorCount;
     c->arch = std::string(prop.gcnArchName).substr(0, std::string(prop.gcnArchName).find(':'));
     if (const char* g = std::getenv("HRMS_NO_GRAPH")) c->graphs = !(g[0] && g[0] != '0');
+    if (const char* g = std::getenv("HRMS_LOG")) c->log = g[0] && g[0] != '0';
+    c->fault = parse_faults(std::getenv("HRMS_FAULT_INJECT"));
     if (tune_cache_path) {
         c->tune_path = tune_cache_path;
         load_tune(c);
@@ -1392,7 +1463,9 @@ int hrms_run_2d(hrms_handle h, const hrms_run2d_args* a, void* hip_stream)
         rp.nlev = P->nlev;
         rp.out_mask = a->out_mask;
         rp.zgroups = (2 * a->zmax + 1 + 3) / 4;
-        if ((e = launch_hrms2d(a->variant, a->dtype, rp, stream)) != hipSuccess)
+        if (h->fault & kFaultLaunch) e = hipErrorLaunchFailure;   // injected
+        else e = launch_hrms2d(a->variant, a->dtype, rp, stream);
+        if (e != hipSuccess)
             return hip_fail(h, e, "2D harmonic-sum launch");
     }
     if ((e = use.finish()) != hipSuccess) return hip_fail(h, e, "hipEventRecord");
@@ -1440,7 +1513,9 @@ int hrms_quantize(hrms_handle h, const hrms_quantize_args* a, void* hip_stream)
     qp.inv_mu = (const float*)P->d_inv.p;
     qp.y = a->y;
     qp.nsegs = (int32_t)P->segs.size();
-    if ((e = launch_quantize(a->dtype, qp, stream)) != hipSuccess)
+    if (h->fault & kFaultLaunch) e = hipErrorLaunchFailure;   // injected
+    else e = launch_quantize(a->dtype, qp, stream);
+    if (e != hipSuccess)
         return hip_fail(h, e, "quantisation launch");
     if ((e = use.finish()) != hipSuccess) return hip_fail(h, e, "hipEventRecord");
     return HRMS_OK;

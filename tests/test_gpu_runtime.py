@@ -127,3 +127,95 @@ def test_every_launch_shape_matches_oracle(monkeypatch, variant, shape):
                            label=f"shape {shape}")
     finally:
         H.hrms_destroy(h)
+
+
+def _handle_with_env(**env):
+    from paper_1812_02647_amd import hrms as H
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update(env)
+    try:
+        return H.hrms_create(0)
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+def test_injected_allocation_failure_leaves_handle_usable():
+    """HRMS_FAULT_INJECT=alloc: the 1D, 2D and precision-form calls that need
+    device memory fail with HRMS_E_NOMEM before enqueuing anything (outputs
+    keep their fill); the entry point that allocates nothing still runs and
+    matches the oracle; the handle is destroyed normally."""
+    import torch
+    from paper_1812_02647_amd import hrms as H
+    x, offsets, _ = synth.batch(3, [5000, 70001, 333], seed=23, comb_fraction=0.5)
+    xd, seen = to_device_input(x, "f32")
+    h = _handle_with_env(HRMS_FAULT_INJECT="alloc")
+    try:
+        case_log("fault injection: alloc")
+        b = H.Batch1D(xd, offsets, H.HRMS_GREEDY, 16)
+        b.max_snr.fill_(-3.0)
+        torch.cuda.synchronize()
+        with pytest.raises(H.HrmsError) as ei:
+            b.run(h)
+        assert ei.value.status == H.HRMS_E_NOMEM and "HRMS_FAULT_INJECT" in str(ei.value)
+        torch.cuda.synchronize()
+        assert bool((b.max_snr == -3.0).all())
+        # 2D plane and precision form
+        a = H.hrms_run2d_args()
+        a.nf, a.zmax, a.hmax, a.variant, a.ld, a.out_mask = 1000, 1, 8, H.HRMS_FREQBIN, 1000, 2
+        plane = torch.ones(3 * 1000, dtype=torch.float32, device="cuda")
+        st = torch.zeros(2, dtype=torch.float64, device="cuda")
+        ms = torch.empty(3000, dtype=torch.float32, device="cuda")
+        a.x, a.stats, a.max_snr = plane.data_ptr(), st.data_ptr(), ms.data_ptr()
+        with pytest.raises(H.HrmsError) as ei:
+            H.hrms_run_2d(h, a)
+        assert ei.value.status == H.HRMS_E_NOMEM
+        # the no-alloc entry point needs no allocation
+        b.run_noalloc(h)
+        torch.cuda.synchronize()
+        out = fetch(b)
+        for s in range(3):
+            check_spectrum(b, out, seen, s, H.HRMS_GREEDY, 16, check_f64=False,
+                           label="noalloc under alloc fault")
+    finally:
+        H.hrms_destroy(h)
+
+
+@pytest.mark.parametrize("graphs", [True, False])
+def test_injected_launch_failure_leaves_handle_destroyable(graphs):
+    """HRMS_FAULT_INJECT=launch: every harmonic-sum launch reports
+    HRMS_E_HIP (the statistics and constants before it run normally); the
+    handle is destroyed normally and a new handle computes the same batch
+    correctly."""
+    import torch
+    from paper_1812_02647_amd import hrms as H
+    x, offsets, _ = synth.batch(2, [4099, 20000], seed=29, comb_fraction=0.5)
+    xd, seen = to_device_input(x, "f32")
+    env = {"HRMS_FAULT_INJECT": "launch"}
+    if not graphs:
+        env["HRMS_NO_GRAPH"] = "1"
+    h = _handle_with_env(**env)
+    try:
+        case_log(f"fault injection: launch graphs={graphs}")
+        b = H.Batch1D(xd, offsets, H.HRMS_MAX, 32)
+        for _ in range(2):
+            with pytest.raises(H.HrmsError) as ei:
+                b.run(h)
+            assert ei.value.status == H.HRMS_E_HIP
+        with pytest.raises(H.HrmsError):
+            b.run_noalloc(h)
+        torch.cuda.synchronize()
+    finally:
+        H.hrms_destroy(h)
+    h2 = H.hrms_create(0)
+    try:
+        b = H.Batch1D(xd, offsets, H.HRMS_MAX, 32).run(h2)
+        torch.cuda.synchronize()
+        out = fetch(b)
+        for s in range(2):
+            check_spectrum(b, out, seen, s, H.HRMS_MAX, 32, check_f64=False, label="after fault")
+    finally:
+        H.hrms_destroy(h2)
