@@ -14,6 +14,11 @@
    another path, so its error is only reported.
 3. Candidate lists {n : max_snr >= 6} of narrow storage and FP32 storage
    mostly agree, and every injected comb that FP32 storage finds is found.
+4. Against the binary64 oracle: the same error bound on the 2D plane (eq. (1),
+   Max, freq-bin; Greedy and Greedy with fdot drift reported), and the
+   candidate lists at SNR >= 6 of FP32, FP16 and BF16 storage in 1D and 2D
+   (Jaccard index, missed and extra bins, best-H agreement on the shared
+   ones), every variant bounded from below by the measured agreement.
 """
 import math
 
@@ -152,7 +157,7 @@ def test_candidate_lists_agree(handle, dtype):
         c16 = set(np.nonzero(o16["max_snr"] >= 6.0)[0].tolist())
         c32 = set(np.nonzero(o32["max_snr"] >= 6.0)[0].tolist())
         jac = len(c16 & c32) / max(1, len(c16 | c32))
-        assert jac > (0.95 if dtype == "f16" else 0.7), (NAMES[v], dtype, jac)
+        assert jac > (0.99 if dtype == "f16" else 0.97), (NAMES[v], dtype, jac)
         # an injected comb found with FP32 storage is found with narrow storage
         for s, f0 in combs:
             if v == 0:
@@ -160,3 +165,165 @@ def test_candidate_lists_agree(handle, dtype):
             near = [offsets[s] + int(math.floor(f0)) + d for d in (-1, 0, 1)]
             if any(n in c32 for n in near):
                 assert any(n in c16 for n in near), (NAMES[v], dtype, s, f0)
+
+
+# --------------------------------------------------------------------------
+# Against the binary64 oracle: the plane's error study and the candidate
+# lists at SNR >= 6 (1D and 2D). The reference for narrow storage is the
+# oracle's binary64 evaluation on the exact normalised input x / mu with
+# statistics (1, sigma / mu); for FP32 storage, its binary64 evaluation on x.
+# --------------------------------------------------------------------------
+
+def _list_compare(got_ms, got_bh, ref_ms, ref_bh, thr=6.0):
+    """Jaccard index, missed and extra bins, best-H agreement on the shared."""
+    g = set(np.nonzero(got_ms >= thr)[0].tolist())
+    r = set(np.nonzero(ref_ms >= thr)[0].tolist())
+    both = g & r
+    agree = sum(int(got_bh[k]) == int(ref_bh[k]) for k in both)
+    return {"oracle": len(r), "device": len(g), "jaccard": len(both) / max(1, len(g | r)),
+            "missed": len(r - g), "extra": len(g - r),
+            "best_h_agree": agree / max(1, len(both))}
+
+
+def _oracle_f64_lists(x, offsets, variant, hmax, scale_stats=None):
+    """Binary64 max-SNR and best-H of every bin of a packed batch."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    def one(s):
+        xs = x[offsets[s]:offsets[s + 1]].astype(np.float64)
+        if scale_stats is not None:
+            mu_raw = scale_stats[s][0]
+            xs = xs / mu_raw
+            mu, sd = 1.0, scale_stats[s][1] / mu_raw
+        else:
+            mu, sd = O.stats(xs)
+        _, ms, bh, _ = O.hrms_1d(xs, variant, hmax, f32=False, mu=mu, sigma=sd)
+        return ms, bh
+
+    with ThreadPoolExecutor(max_workers=8) as ex:
+        parts = list(ex.map(one, range(offsets.size - 1)))
+    return np.concatenate([p[0] for p in parts]), np.concatenate([p[1] for p in parts])
+
+
+# Lower bounds of the Jaccard index against the binary64 oracle, set below
+# the measured values (4 spectra of 2^20 bins, half with combs; about 4200
+# to 4900 candidates per variant): FP32 storage 1.0 for every variant (no
+# FP32 rounding moved an SNR across the threshold), FP16 0.998, BF16 0.986,
+# Greedy included. Narrow storage loses bins just above the threshold (the
+# stored bins move their SNR), more than it gains.
+JACCARD_1D = {"f32": 0.999, "f16": 0.99, "bf16": 0.97}
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
+def test_candidate_lists_vs_binary64_oracle_1d(handle, dtype):
+    import torch
+    x, offsets, combs = synth.batch(4, 1 << 20, seed=82, comb_fraction=0.5)
+    xd = torch.from_numpy(x).to("cuda")
+    case_log(f"candidate lists vs binary64 oracle 1D dtype={dtype}")
+    if dtype == "f32":
+        inp, stats, scale = xd, None, None
+    else:
+        inp, st, so = quantize(handle, xd, offsets, dtype)
+        stats = torch.from_numpy(so).to("cuda")
+        scale = st
+    report = {}
+    for v in [0, 1, 2, 3]:
+        o = fetch(run_1d(handle, inp, offsets, v, 32, stats=stats))
+        ref_ms, ref_bh = _oracle_f64_lists(x, offsets, v, 32, scale)
+        c = _list_compare(o["max_snr"], o["best_h"], ref_ms, ref_bh)
+        report[NAMES[v]] = c
+        assert c["oracle"] > 1000
+        assert c["jaccard"] >= JACCARD_1D[dtype], (NAMES[v], dtype, c)
+        assert c["best_h_agree"] >= 0.99, (NAMES[v], dtype, c)
+    print(f"1D candidates at SNR >= 6 vs binary64 oracle, {dtype}:",
+          {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in c.items()}
+           for k, c in report.items()})
+
+
+def _quantize_plane(handle, xdev2d, dtype):
+    import torch
+    rows, nf = xdev2d.shape
+    offsets = np.array([0, rows * nf], np.int64)
+    y, st, so = quantize(handle, xdev2d.reshape(-1), offsets, dtype)
+    return y.reshape(rows, nf), st[0], so[0]
+
+
+# (u, whether the bound of item 2 applies): eq. (1), Max and freq-bin are
+# bounded; Greedy and Greedy with fdot drift may take another path.
+@pytest.mark.parametrize("dtype,u", [("f16", 2.0 ** -10), ("bf16", 2.0 ** -7)])
+def test_plane_narrow_storage_error_bound(handle, dtype, u):
+    import torch
+    from tests.test_gpu_parity_2d import run_2d
+    zmax, nf, hmax = 7, 1 << 18, 16
+    x, _ = synth.plane(nf=nf, zmax=zmax, seed=91, n_comb=6, f0_max=nf // 20)
+    xd = torch.from_numpy(x).to("cuda")
+    case_log(f"plane precision error study dtype={dtype}")
+    y, st, so = _quantize_plane(handle, xd, dtype)
+    xs = x.astype(np.float64) / st[0]          # exact normalised plane
+    stats = torch.tensor(so, dtype=torch.float64, device="cuda")
+    rng = np.random.default_rng(5)
+    fidx = np.concatenate([np.arange(0, 48), rng.integers(0, nf // hmax, 1500),
+                           rng.integers(0, nf, 1500)]).astype(np.int64)
+    zidx = rng.integers(-zmax, zmax + 1, fidx.size).astype(np.int32)
+    # the smallest bins of the plane, at H = 1 (FP16 subnormals)
+    small = np.argsort(xs.ravel())[:32]
+    fidx = np.concatenate([fidx, small % nf]).astype(np.int64)
+    zidx = np.concatenate([zidx, small // nf - zmax]).astype(np.int32)
+    r = zidx.astype(np.int64) + zmax
+    report = {}
+    for v in [0, 1, 2, 3, 5]:
+        out = run_2d(handle, y, nf, zmax, hmax, v, stats=stats)
+        h64, _, _, _ = O.hrms_2d(xs, zmax, v, hmax, fidx=fidx, zidx=zidx, f32=False,
+                                 want_snr=False)
+        worst, ratio = [], []
+        for l in range(O.num_levels(hmax)):
+            H = 1 << l
+            ln = nf if v == 0 else nf >> l
+            valid = fidx < ln
+            got = out["h"][out["offs"][l] + r[valid] * ln + fidx[valid]].astype(np.float64)
+            ref = h64[l][valid]
+            err = np.abs(got - ref)
+            bound = (u / 2 + (H + 2) * 2.0 ** -24) * np.abs(ref) + H * 2.0 ** -25
+            worst.append(float(np.max(err / np.maximum(np.abs(ref), 1e-300))))
+            ratio.append(float(np.max(err / bound)))
+        report[NAMES[v]] = [float(f"{w:.3g}") for w in worst]
+        if v in (0, 1, 2):
+            assert max(ratio) <= 1.0, (dtype, NAMES[v], ratio, worst)
+    print(f"plane max relative error vs binary64, {dtype}:", report)
+
+
+# measured on a 15 x 2^17 plane (2000 to 2700 candidates per variant): FP32
+# storage 1.0, FP16 0.9995 to 1.0, BF16 0.991 to 0.993, Greedy and Greedy with
+# fdot drift included
+JACCARD_2D = {"f32": 0.999, "f16": 0.99, "bf16": 0.98}
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
+def test_candidate_lists_vs_binary64_oracle_2d(handle, dtype):
+    import torch
+    from tests.test_gpu_parity_2d import run_2d
+    zmax, nf, hmax = 7, 1 << 17, 16
+    x, _ = synth.plane(nf=nf, zmax=zmax, seed=92, n_comb=8, f0_max=nf // 20)
+    xd = torch.from_numpy(x).to("cuda")
+    case_log(f"candidate lists vs binary64 oracle 2D dtype={dtype}")
+    if dtype == "f32":
+        inp, stats = xd, None
+        xs = x.astype(np.float64)
+        mu, sd = O.stats(xs)
+    else:
+        inp, st, so = _quantize_plane(handle, xd, dtype)
+        stats = torch.tensor(so, dtype=torch.float64, device="cuda")
+        xs = x.astype(np.float64) / st[0]
+        mu, sd = 1.0, st[1] / st[0]
+    report = {}
+    for v in [0, 1, 2, 3, 5]:
+        out = run_2d(handle, inp, nf, zmax, hmax, v, stats=stats)
+        _, ms64, bh64, _ = O.hrms_2d(xs, zmax, v, hmax, f32=False, mu=mu, sigma=sd)
+        c = _list_compare(out["max_snr"], out["best_h"], ms64, bh64)
+        report[NAMES[v]] = c
+        assert c["oracle"] > 200
+        assert c["jaccard"] >= JACCARD_2D[dtype], (NAMES[v], dtype, c)
+        assert c["best_h_agree"] >= 0.99, (NAMES[v], dtype, c)
+    print(f"2D candidates at SNR >= 6 vs binary64 oracle, {dtype}:",
+          {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in c.items()}
+           for k, c in report.items()})
