@@ -660,6 +660,11 @@ def workload_plane(args):
     torch.cuda.synchronize()
     res16 = timed(y, H.HRMS_F16, stats=st_out.reshape(2))
     tot16 = sum(r["ms"] for r in res16.values())
+    if args.calibrate_copy and args.workload == "plane":
+        c = torch.empty_like(xd)
+        c.copy_(xd)
+        torch.cuda.synchronize()
+        del c
     H.hrms_destroy(handle)
     return {"metric": METRIC, "value": round(rows * nf / tot_ms / 1e6, 3),
             "unit": "G input bins/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,

@@ -73,6 +73,10 @@
  *                          (HRMS_E_HIP; the statistics and constants launches
  *                          before it may have been enqueued); the handle stays
  *                          usable and destroyable
+ *   HRMS_FORCE_SHAPE=wg:r:chunk[:top], HRMS_INFLIGHT_OUTPUTS=n
+ *                          tuning overrides of the 1D launch shape and of the
+ *                          outputs in flight per CU on large spectra (0: no
+ *                          limit); results are the same bits
  */
 #ifndef HRMS_H
 #define HRMS_H

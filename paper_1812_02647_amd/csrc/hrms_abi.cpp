@@ -653,7 +653,8 @@ int plan_host_1d(hrms_ctx* c, const hrms_run1d_args* a, const Shape1D& shape, Pl
         if (per_cu <= 0)
             return hip_fail(c, oe != hipSuccess ? oe : hipErrorInvalidConfiguration,
                             "occupancy query of the 1D kernel");
-        const int lim = inflight_outputs_per_cu(a->variant, a->dtype);
+        int lim = inflight_outputs_per_cu(a->variant, a->dtype);
+        if (const char* f = std::getenv("HRMS_INFLIGHT_OUTPUTS")) lim = std::atoi(f);   // tuning
         if (part == 0 && l2_bound && lim > 0)
             per_cu = std::min(per_cu, std::max(1, lim / hrms1d_tile_outputs(a->variant, shape)));
         int64_t grid = std::min<int64_t>((int64_t)c->cu_count * per_cu, (int64_t)tiles.size());
