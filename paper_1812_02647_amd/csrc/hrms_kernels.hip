@@ -1428,6 +1428,7 @@ __global__ __launch_bounds__(WG) void k_hrms1d_win(const Run1DParams p)
 // read the same columns.
 // --------------------------------------------------------------------------
 constexpr int kZRows = 4;
+constexpr unsigned kXcds = 8;   // XCDs of the part, taking workgroups in turn
 
 __device__ __forceinline__ int row_of(int iz, int l)
 {
@@ -1453,8 +1454,14 @@ __global__ __launch_bounds__(64 * kZRows) void k_hrms2d(const Run2DParams p)
     // the fdot row is the same for the whole wavefront, so every row a
     // harmonic reads is a scalar and its loads go through a scalar resource
     const int zl = uniform((int)threadIdx.x >> 6);
-    const int zg = (int)(blockIdx.x % (unsigned)p.zgroups);
-    const int mb = (int)(blockIdx.x / (unsigned)p.zgroups);
+    // Workgroup b runs on XCD b mod 8. Each XCD takes whole frequency blocks
+    // with all their fdot groups (block 8 j + x of the frequency axis on XCD
+    // x), so the columns that the rows of one block read are fetched into one
+    // L2 and shared there by all its fdot groups, while the eight XCDs still
+    // work on neighbouring frequency blocks.
+    const unsigned xcd = blockIdx.x % kXcds, slot = blockIdx.x / kXcds;
+    const int zg = (int)(slot % (unsigned)p.zgroups);
+    const int mb = (int)((slot / (unsigned)p.zgroups) * kXcds + xcd);
     const int rows = 2 * p.zmax + 1;
     const int r = zg * kZRows + zl;
     const int m = mb * 64 + lane;
@@ -1885,8 +1892,10 @@ Kernel2D kernel_2d(int dtype)
 
 hipError_t launch_hrms2d(int variant, int dtype, const Run2DParams& p, hipStream_t s)
 {
+    // frequency blocks rounded up to whole rounds of the XCDs (the blocks
+    // past the plane's end return at once)
     const int64_t mblocks = ((int64_t)p.nf + 63) / 64;
-    const int64_t blocks = mblocks * p.zgroups;
+    const int64_t blocks = (mblocks + kXcds - 1) / kXcds * kXcds * p.zgroups;
     if (blocks <= 0) return hipSuccess;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     dim3 grid((unsigned)blocks), block(64 * kZRows);
