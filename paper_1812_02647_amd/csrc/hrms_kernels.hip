@@ -1039,33 +1039,63 @@ __device__ void level_consts(int variant, double mu, double sigma, int H, double
     *q_out = s > 0.0 ? 1.0 / s : 0.0;
 }
 
+// Sums of a spectrum's segment partials by one wave: lane j adds segments
+// j, j + 64, ... in order, then a fixed tree halves the lanes; lane 0's
+// result is returned to every lane. The order depends only on the spectrum's
+// own segments, so repeated runs and any packing give the same bits.
+__device__ __forceinline__ void wave_partial_sums(const double* partial, int first, int last,
+                                                  int lane, double& t1, double& t2)
+{
+    double a = 0.0, b = 0.0;
+    for (int g = first + lane; g < last; g += 64) {
+        a = a + partial[2 * (int64_t)g];
+        b = b + partial[2 * (int64_t)g + 1];
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        const double ao = __shfl_down(a, d, 64);
+        const double bo = __shfl_down(b, d, 64);
+        if (lane < d) {
+            a = a + ao;
+            b = b + bo;
+        }
+    }
+    t1 = __shfl(a, 0, 64);
+    t2 = __shfl(b, 0, 64);
+}
+
+// One wave per spectrum: statistics (reduced, or read when provided) and the
+// per-level constants, lane l < 6 computing level l's.
 __global__ __launch_bounds__(64) void k_consts(const ConstsParams p)
 {
-    const int s = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (s == 0 && p.counters)
-        for (int q = 0; q < kCounterSlots; ++q) p.counters[q] = 0u;
-    if (s == 0 && p.cand_count) *p.cand_count = 0u;
+    const int s = (int)blockIdx.x;
+    const int lane = (int)threadIdx.x;
+    if (s == 0 && lane == 0) {
+        if (p.counters)
+            for (int q = 0; q < kCounterSlots; ++q) p.counters[q] = 0u;
+        if (p.cand_count) *p.cand_count = 0u;
+    }
     if (s >= p.n_spec) return;
     const SpecDesc sd = p.spec[s];
     double mu, sigma;
     if (p.compute_stats) {
-        double t1 = 0.0, t2 = 0.0;
-        for (int g = p.seg_first[s]; g < p.seg_first[s + 1]; ++g) {
-            t1 = t1 + p.partial[2 * (int64_t)g];
-            t2 = t2 + p.partial[2 * (int64_t)g + 1];
-        }
+        double t1, t2;
+        wave_partial_sums(p.partial, p.seg_first[s], p.seg_first[s + 1], lane, t1, t2);
         const double nb = (double)sd.n;
         mu = t1 / nb;
         double var = t2 / nb - mu * mu;
         if (var < 0.0) var = 0.0;
         sigma = sqrt(var);
-        p.stats[2 * (int64_t)s] = mu;
-        p.stats[2 * (int64_t)s + 1] = sigma;
+        if (lane == 0) {
+            p.stats[2 * (int64_t)s] = mu;
+            p.stats[2 * (int64_t)s + 1] = sigma;
+        }
     } else {
         mu = p.stats[2 * (int64_t)s];
         sigma = p.stats[2 * (int64_t)s + 1];
     }
-    for (int l = 0; l < kMaxLevels; ++l) {
+    const int l = lane;
+    if (l < kMaxLevels) {
         float m32 = 0.0f, q32 = 0.0f;
         if (l < sd.nlev) {
             double m, q;
@@ -1628,22 +1658,23 @@ __global__ __launch_bounds__(kPeakWG) void k_peaks(const PeakParams pp)
 // --------------------------------------------------------------------------
 __global__ __launch_bounds__(64) void k_quant_consts(const QuantConstParams p)
 {
-    const int s = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    // one wave per spectrum, as k_consts
+    const int s = (int)blockIdx.x;
+    const int lane = (int)threadIdx.x;
     if (s >= p.n_spec) return;
     double mu, sigma;
     if (p.compute_stats) {
-        double t1 = 0.0, t2 = 0.0;
-        for (int g = p.seg_first[s]; g < p.seg_first[s + 1]; ++g) {
-            t1 = t1 + p.partial[2 * (int64_t)g];
-            t2 = t2 + p.partial[2 * (int64_t)g + 1];
-        }
+        double t1, t2;
+        wave_partial_sums(p.partial, p.seg_first[s], p.seg_first[s + 1], lane, t1, t2);
         const double nb = (double)p.spec[s].n;
         mu = t1 / nb;
         double var = t2 / nb - mu * mu;
         if (var < 0.0) var = 0.0;
         sigma = sqrt(var);
-        p.stats[2 * (int64_t)s] = mu;
-        p.stats[2 * (int64_t)s + 1] = sigma;
+        if (lane == 0) {
+            p.stats[2 * (int64_t)s] = mu;
+            p.stats[2 * (int64_t)s + 1] = sigma;
+        }
     } else {
         mu = p.stats[2 * (int64_t)s];
         sigma = p.stats[2 * (int64_t)s + 1];
@@ -1651,9 +1682,11 @@ __global__ __launch_bounds__(64) void k_quant_consts(const QuantConstParams p)
     // a spectrum whose mean is not a positive finite number cannot be scaled
     // to unit mean: it is stored unscaled, with its own statistics
     const bool scalable = mu > 0.0 && mu <= 1.79769313486231570e308;
-    p.stats_out[2 * (int64_t)s] = scalable ? 1.0 : mu;
-    p.stats_out[2 * (int64_t)s + 1] = scalable ? sigma / mu : sigma;
-    p.inv_mu[s] = scalable ? (float)(1.0 / mu) : 1.0f;
+    if (lane == 0) {
+        p.stats_out[2 * (int64_t)s] = scalable ? 1.0 : mu;
+        p.stats_out[2 * (int64_t)s + 1] = scalable ? sigma / mu : sigma;
+        p.inv_mu[s] = scalable ? (float)(1.0 / mu) : 1.0f;
+    }
 }
 
 __device__ __forceinline__ uint16_t to_f16_sat(float v)
@@ -1810,7 +1843,8 @@ hipError_t launch_stats_partial(int dtype, const StatsParams& p, hipStream_t s)
 
 hipError_t launch_consts(const ConstsParams& p, hipStream_t s)
 {
-    const int blocks = (p.n_spec + 63) / 64;
+    // one wave per spectrum (at least one, which also resets the counters)
+    const int blocks = p.n_spec > 0 ? p.n_spec : 1;
     hipLaunchKernelGGL(k_consts, dim3(blocks), dim3(64), 0, s, p);
     return hipGetLastError();
 }
@@ -1921,7 +1955,7 @@ hipError_t launch_peaks(const PeakParams& p, hipStream_t s)
 
 hipError_t launch_quant_consts(const QuantConstParams& p, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_quant_consts, dim3((p.n_spec + 63) / 64), dim3(64), 0, s, p);
+    hipLaunchKernelGGL(k_quant_consts, dim3(p.n_spec > 0 ? p.n_spec : 1), dim3(64), 0, s, p);
     return hipGetLastError();
 }
 
