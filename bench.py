@@ -85,18 +85,21 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_1812_02647_amd", "csrc", f)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
-def measured_traffic(kernel: str, variant: str):
-    """HBM bytes per launch of the dominant kernel from the committed counter
-    runs (FETCH_SIZE, WRITE_SIZE, each scaled by what the counter reads for a
-    copy of known size), or None if they were taken on other kernel sources."""
+def measured_traffic(workload: str, variant: str, dtype: str = "f32"):
+    """HBM bytes (read + written) per launch of a variant's kernels on a
+    workload, from the committed counter runs (FETCH_SIZE, WRITE_SIZE, each
+    scaled by what the counter reads for a copy of known size), or None if
+    they were taken on other kernel sources."""
     import hashlib
     try:
         rec = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
     digest = hashlib.sha256(b"".join(open(f, "rb").read() for f in KERNEL_SOURCES)).hexdigest()
-    for ent in rec.get("kernels", []):
-        if ent.get("source_sha256") == digest and ent.get("variant") == variant:
+    if rec.get("source_sha256") != digest:
+        return None
+    for ent in rec.get("entries", []):
+        if (ent.get("workload"), ent.get("variant"), ent.get("dtype")) == (workload, variant, dtype):
             return ent["read_bytes"] + ent["write_bytes"]
     return None
 
@@ -174,6 +177,8 @@ class Runner:
         self.ms = torch.empty(total, dtype=torch.float32, device=dev)
         self.bh = torch.empty(total, dtype=torch.uint8, device=dev)
         self.in_bytes = xd.element_size()
+        # the counter records are of the 1000 x 2^21, Hmax = 32 batch
+        self.default_batch = (ns == 1000 and total == 1000 * (1 << 21) and hmax == 32)
 
         def make(v, mode, mask):
             a = H.hrms_run1d_args()
@@ -218,12 +223,15 @@ class Runner:
         for k, v in enumerate(self.variants):
             t = float(np.mean([e[1 + k].elapsed_time(e[2 + k]) for e in ev]))
             byts = alg_bytes_per_launch(self.total, self.layouts[v], self.in_bytes)
-            per[VARIANT_NAMES[v]] = {
+            name = VARIANT_NAMES[v]
+            per[name] = {
                 "ms": round(t, 4),
                 "gbins_per_s": round(self.total / (t * 1e-3) / 1e9, 2),
                 "alg_bytes": byts,
                 "achieved_gbs": round(byts / (t * 1e-3) / 1e9, 1),
                 "frac_hbm": round(byts / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "traffic": (measured_traffic("batch", name, "f32" if self.in_bytes == 4 else "f16")
+                            if self.default_batch else None),
             }
         return step_ms, stats_ms, per, wall
 
@@ -508,7 +516,7 @@ def workload_batch(args):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": d["frac_hbm"],
-            "traffic": measured_traffic(KERNEL_OF[dom], dom),
+            "traffic": measured_traffic("batch", dom),
             "copy_ceiling_gbs": round(copy_gbs, 1),
             "frac_of_copy_ceiling": d["frac_copy"],
         },
@@ -639,7 +647,9 @@ def workload_plane(args):
             t = e0.elapsed_time(e1) / args.steps
             byts = rows * nf * plane.element_size() + 4 * tot + 5 * rows * nf
             res[names[v]] = {"ms": round(t, 4), "gbins_per_s": round(rows * nf / t / 1e6, 2),
-                             "alg_bytes": byts, "frac_hbm": round(byts / t / 1e9 / 8.0, 4)}
+                             "alg_bytes": byts, "frac_hbm": round(byts / t / 1e9 / 8.0, 4),
+                             "traffic": measured_traffic(
+                                 "plane", names[v], "f32" if plane.element_size() == 4 else "f16")}
             del hb, ms, bh
         return res
 
