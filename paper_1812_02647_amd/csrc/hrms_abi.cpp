@@ -536,7 +536,7 @@ int plan_host_1d(hrms_ctx* c, const hrms_run1d_args* a, const Shape1D& shape, Pl
                     const int ht = 1 << l;
                     const bool top = shape.top > 0 && ht >= shape.top;
                     const Shape1D& sh = top ? kTopShape : shape;
-                    const int tt = top ? Ttop : hrms1d_band_tile(a->variant, shape, ht);
+                    const int tt = top ? Ttop : hrms1d_band_tile(a->variant, shape, ht, 1 << (g.nlev - 1));
                     const int64_t terms = a->variant == HRMS_MAX || a->variant == HRMS_OPT
                                               ? (int64_t)ht * (ht + 1) / 2
                                               : ht;

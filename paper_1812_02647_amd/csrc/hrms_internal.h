@@ -149,14 +149,21 @@ inline bool hrms1d_window_form(int variant, const Shape1D& s)
 {
     return (variant == 1 || variant == 4) && s.chunk == 0;
 }
-// Tile length of a band whose top level is ht: the window form gives its cheap
-// bands longer tiles so that per-tile work (claim, record, barrier) stays
-// small against the bins they cover.
-inline int hrms1d_band_tile(int variant, const Shape1D& s, int ht)
+// Tile length of a band whose top level is ht, in a spectrum whose top level
+// is htop: the forms without LDS staging give their cheap bands longer tiles
+// so that per-tile work (claim, record, barrier) stays small against the bins
+// they cover. Multiples measured on 1000 x 2^21 FP32 batches: the window form
+// 8x (ht <= 2) and 2x (ht <= 8); freq-bin 2x (ht <= 2; 8x and 2x for ht <= 8
+// were slower); Greedy 8x and 2x below htop = 32 (Hmax 4: 11.9 -> 7.2 ms,
+// 16: 12.6 -> 10.5) but only 2x (ht <= 2) at Hmax 32, where the longer tiles
+// lost 0.6 ms.
+inline int hrms1d_band_tile(int variant, const Shape1D& s, int ht, int htop)
 {
     const int t = hrms1d_tile_outputs(variant, s);
-    if (!hrms1d_window_form(variant, s)) return t;
-    return ht <= 2 ? 8 * t : ht <= 8 ? 2 * t : t;
+    if (s.chunk != 0) return t;
+    const bool wide = hrms1d_window_form(variant, s) || (variant == 3 && htop < 32);
+    if (wide) return ht <= 2 ? 8 * t : ht <= 8 ? 2 * t : t;
+    return ht <= 2 ? 2 * t : t;
 }
 // Resident workgroups per CU of the 1D kernel; 0 (with *err set) on failure.
 int hrms1d_max_blocks_per_cu(int variant, int dtype, const Shape1D& shape, hipError_t* err);

@@ -790,9 +790,10 @@ __global__ __launch_bounds__(WG) void k_hrms1d_eq1(const Run1DParams p)
 }
 
 // --------------------------------------------------------------------------
-// eq. (2)-(4), gathered straight from global memory: a tile is a run of at
-// most T = WG * R outputs of one band; thread t holds outputs a + r WG + t in
-// registers and, for i = 1..Ht in turn, loads the bins of term i of all R
+// eq. (2)-(4), gathered straight from global memory: a tile is a run of
+// outputs of one band, taken WG * R at a time (a tile of a cheap band holds
+// several such runs); thread t holds outputs a + r WG + t of the current run
+// in registers and, for i = 1..Ht in turn, loads the bins of term i of all R
 // outputs at once (positions i n, stepped by n from harmonic to harmonic) with
 // 32-bit-offset buffer loads over the spectrum. Neighbouring outputs read
 // positions i apart, so a wavefront's load covers about 2i cache lines that
@@ -822,9 +823,7 @@ __global__ __launch_bounds__(WG) void k_hrms1d_gather(const Run1DParams p)
         // claim the following tile now; it is read after this tile's barrier
         if (tid == 0) s_claim[(c + 1) & 1] = claim_tile(p, cq, visited);
         const TileRec ct = ldc(p.tiles + t);
-        const int a = ct.a;
         const int ht = 1 << (ct.nlev - 1);
-        const int tn = ct.aend - a;
         if (ct.spec != cur_spec) {
             cur_spec = ct.spec;
             if (lane < kMaxLevels) {
@@ -840,95 +839,101 @@ __global__ __launch_bounds__(WG) void k_hrms1d_gather(const Run1DParams p)
         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
             (void*)(static_cast<const char*>(p.x) + ct.xoff * Elem<DT>::kBytes), (short)0,
             ct.n * Elem<DT>::kBytes, kBufferFlags);
-        const __amdgpu_buffer_rsrc_t mrs = out_rsrc(p.max_snr + ct.xoff + a, tn * 4);
-        const __amdgpu_buffer_rsrc_t brs = out_rsrc(p.best_h + ct.xoff + a, tn);
+        // a tile of the cheap bands holds several runs of WG R outputs,
+        // taken in turn (fewer tiles to claim and fewer barriers per output)
+        for (int a = ct.a; a < ct.aend; a += WG * R) {
+            const int tn = ct.aend - a < WG * R ? ct.aend - a : WG * R;
+            const int aend = a + tn;
+            const __amdgpu_buffer_rsrc_t mrs = out_rsrc(p.max_snr + ct.xoff + a, tn * 4);
+            const __amdgpu_buffer_rsrc_t brs = out_rsrc(p.best_h + ct.xoff + a, tn);
 
-        float acc[R], best[R];
-        int st[R], pos[R], nn[R];
-        bool act[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int n = a + r * WG + tid;
-            act[r] = n < ct.aend;
-            nn[r] = act[r] ? n : a;
-            pos[r] = 0;
-            // Greedy starts from -0 so that its first term passes unchanged
-            acc[r] = VAR == kGreedy ? -0.0f : 0.0f;
-            best[r] = 0.0f;
-            st[r] = 0;
-        }
-        for (int i = 1; i <= ht; ++i) {
-            float tv[R];
-#pragma unroll
-            for (int r = 0; r < R; ++r) pos[r] += nn[r];
-            if constexpr (VAR == kFreqbin) {
-#pragma unroll
-                for (int r = 0; r < R; ++r) tv[r] = buffer_elem<DT>(rs, pos[r]);
-            } else if constexpr (VAR == kMax) {
-#pragma unroll
-                for (int r = 0; r < R; ++r) tv[r] = buffer_elem<DT>(rs, pos[r]);
-                for (int jj = 1; jj < i; ++jj) {
-#pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        const float w = buffer_elem<DT>(rs, pos[r] + jj);
-                        tv[r] = w > tv[r] ? w : tv[r];
-                    }
-                }
-            } else {
-                if (i == 1) {
-#pragma unroll
-                    for (int r = 0; r < R; ++r) tv[r] = buffer_elem<DT>(rs, pos[r]);
-                } else {
-                    float x0[R], x1[R];
-#pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        const int q = pos[r] + (st[r] >> 8);
-                        x0[r] = buffer_elem<DT>(rs, q);
-                        x1[r] = buffer_elem<DT>(rs, q + 1);
-                    }
-#pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        const bool step = x1[r] > x0[r];
-                        tv[r] = step ? x1[r] : x0[r];
-                        st[r] += step ? 256 : 0;
-                    }
-                }
+            float acc[R], best[R];
+            int st[R], pos[R], nn[R];
+            bool act[R];
+    #pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int n = a + r * WG + tid;
+                act[r] = n < aend;
+                nn[r] = act[r] ? n : a;
+                pos[r] = 0;
+                // Greedy starts from -0 so that its first term passes unchanged
+                acc[r] = VAR == kGreedy ? -0.0f : 0.0f;
+                best[r] = 0.0f;
+                st[r] = 0;
             }
-#pragma unroll
-            for (int r = 0; r < R; ++r) acc[r] = acc[r] + tv[r];
-            if ((i & (i - 1)) == 0) {
-                const int li = __builtin_ctz((unsigned)i);
-                const float rh =
-                    __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lrh), li));
-                const float m0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lm), li));
-                const float q0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lq), li));
-                const int64_t ho =
-                    (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane(lho_hi, li) << 32) |
-                              (uint32_t)__builtin_amdgcn_readlane(lho_lo, li));
-                const __amdgpu_buffer_rsrc_t hrs = out_rsrc(p.h + ho + a, tn * 4);
-                const bool fin = i == ht;
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const float hv = acc[r] * rh;
-                    const float snr = (hv - m0) * q0;
-                    if (li == 0 || snr > best[r]) {
-                        best[r] = snr;
-                        st[r] = (st[r] & ~255) | li;
-                    }
-                    if (act[r]) {
-                        if (p.out_mask & 1u)
-                            stream_store_b32(__float_as_uint(hv), hrs, tid * 4, r * WG * 4);
-                        if (fin && track) {
-                            if (p.out_mask & 2u)
-                                stream_store_b32(__float_as_uint(best[r]), mrs, tid * 4,
-                                                 r * WG * 4);
-                            if (p.out_mask & 4u)
-                                stream_store_b8((uint8_t)(1u << (st[r] & 255)), brs, tid, r * WG);
+            for (int i = 1; i <= ht; ++i) {
+                float tv[R];
+    #pragma unroll
+                for (int r = 0; r < R; ++r) pos[r] += nn[r];
+                if constexpr (VAR == kFreqbin) {
+    #pragma unroll
+                    for (int r = 0; r < R; ++r) tv[r] = buffer_elem<DT>(rs, pos[r]);
+                } else if constexpr (VAR == kMax) {
+    #pragma unroll
+                    for (int r = 0; r < R; ++r) tv[r] = buffer_elem<DT>(rs, pos[r]);
+                    for (int jj = 1; jj < i; ++jj) {
+    #pragma unroll
+                        for (int r = 0; r < R; ++r) {
+                            const float w = buffer_elem<DT>(rs, pos[r] + jj);
+                            tv[r] = w > tv[r] ? w : tv[r];
                         }
                     }
-                    if (CAND && fin)
-                        append_candidates(p, cands, act[r] && best[r] >= p.cand_thr, ct.spec,
-                                          nn[r], best[r], 1 << (st[r] & 255));
+                } else {
+                    if (i == 1) {
+    #pragma unroll
+                        for (int r = 0; r < R; ++r) tv[r] = buffer_elem<DT>(rs, pos[r]);
+                    } else {
+                        float x0[R], x1[R];
+    #pragma unroll
+                        for (int r = 0; r < R; ++r) {
+                            const int q = pos[r] + (st[r] >> 8);
+                            x0[r] = buffer_elem<DT>(rs, q);
+                            x1[r] = buffer_elem<DT>(rs, q + 1);
+                        }
+    #pragma unroll
+                        for (int r = 0; r < R; ++r) {
+                            const bool step = x1[r] > x0[r];
+                            tv[r] = step ? x1[r] : x0[r];
+                            st[r] += step ? 256 : 0;
+                        }
+                    }
+                }
+    #pragma unroll
+                for (int r = 0; r < R; ++r) acc[r] = acc[r] + tv[r];
+                if ((i & (i - 1)) == 0) {
+                    const int li = __builtin_ctz((unsigned)i);
+                    const float rh =
+                        __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lrh), li));
+                    const float m0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lm), li));
+                    const float q0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lq), li));
+                    const int64_t ho =
+                        (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane(lho_hi, li) << 32) |
+                                  (uint32_t)__builtin_amdgcn_readlane(lho_lo, li));
+                    const __amdgpu_buffer_rsrc_t hrs = out_rsrc(p.h + ho + a, tn * 4);
+                    const bool fin = i == ht;
+    #pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const float hv = acc[r] * rh;
+                        const float snr = (hv - m0) * q0;
+                        if (li == 0 || snr > best[r]) {
+                            best[r] = snr;
+                            st[r] = (st[r] & ~255) | li;
+                        }
+                        if (act[r]) {
+                            if (p.out_mask & 1u)
+                                stream_store_b32(__float_as_uint(hv), hrs, tid * 4, r * WG * 4);
+                            if (fin && track) {
+                                if (p.out_mask & 2u)
+                                    stream_store_b32(__float_as_uint(best[r]), mrs, tid * 4,
+                                                     r * WG * 4);
+                                if (p.out_mask & 4u)
+                                    stream_store_b8((uint8_t)(1u << (st[r] & 255)), brs, tid, r * WG);
+                            }
+                        }
+                        if (CAND && fin)
+                            append_candidates(p, cands, act[r] && best[r] >= p.cand_thr, ct.spec,
+                                              nn[r], best[r], 1 << (st[r] & 255));
+                    }
                 }
             }
         }
