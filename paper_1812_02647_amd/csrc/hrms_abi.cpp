@@ -427,13 +427,15 @@ constexpr int64_t kL2HalfBytes = 2 << 20;
 // an XCD works through whole spectra, and once the input lines that its tiles
 // in flight read no longer fit its L2, more resident workgroups only add
 // re-reads through the fabric. Measured on 2^21-bin FP32 spectra at
-// Hmax = 32 (Greedy 21.7 -> 14.7 ms, freq-bin 19.5 -> 18.6, Max 23.0 -> 22.0);
-// 2-byte bins halve the lines, so twice the outputs. 0: no limit.
-int inflight_outputs_per_cu(int variant, int dtype)
+// Hmax = 32 (Greedy 21.7 -> 14.7 ms, Max 23.0 -> 22.0, freq-bin in the
+// gathered form 23.2 -> 15.3 at 4096 outputs; at Hmax = 16 freq-bin is faster
+// with 8192, 11.0 -> 10.7); 2-byte bins halve the lines, so twice the
+// outputs. htop is the plan's largest top level. 0: no limit.
+int inflight_outputs_per_cu(int variant, int dtype, int htop)
 {
     int f32 = 0;
     if (variant == HRMS_MAX) f32 = 6144;
-    else if (variant == HRMS_FREQBIN) f32 = 8192;
+    else if (variant == HRMS_FREQBIN) f32 = htop >= 32 ? 4096 : 8192;
     else if (variant == HRMS_GREEDY) f32 = 4096;
     return dtype == HRMS_F32 ? f32 : 2 * f32;
 }
@@ -446,7 +448,7 @@ Shape1D default_shape(int variant, int dtype)
     if (variant == HRMS_GREEDY)   // 2-byte bins halve the lines: more outputs per workgroup pay
         return dtype == HRMS_F32 ? Shape1D{256, 8, 0, 0} : Shape1D{512, 8, 0, 0};
     if (variant == HRMS_OPT) return kOptShape;
-    return Shape1D{512, 8, 0, 32};
+    return Shape1D{512, 8, 0, 0};
 }
 
 template <typename T>
@@ -642,6 +644,10 @@ int plan_host_1d(hrms_ctx* c, const hrms_run1d_args* a, const Shape1D& shape, Pl
         if ((int64_t)sd.n * elem_bytes >= kL2HalfBytes) big_bins += sd.n;
     }
     const bool l2_bound = 2 * big_bins >= all_bins;
+    // largest top level of the main launch's bands
+    int htop = 1;
+    for (int s = 0; s < ns; ++s) htop = std::max(htop, 1 << (P->nlev[s] - 1));
+    if (shape.top > 0) htop = std::min(htop, shape.top / 2);
     for (int part = 0; part < 2; ++part) {
         const std::vector<TileRec>& tiles = part ? P->tiles_top : P->tiles;
         int& grid_out = part ? P->grid_top : P->grid;
@@ -653,7 +659,7 @@ int plan_host_1d(hrms_ctx* c, const hrms_run1d_args* a, const Shape1D& shape, Pl
         if (per_cu <= 0)
             return hip_fail(c, oe != hipSuccess ? oe : hipErrorInvalidConfiguration,
                             "occupancy query of the 1D kernel");
-        int lim = inflight_outputs_per_cu(a->variant, a->dtype);
+        int lim = inflight_outputs_per_cu(a->variant, a->dtype, htop);
         if (const char* f = std::getenv("HRMS_INFLIGHT_OUTPUTS")) lim = std::atoi(f);   // tuning
         if (part == 0 && l2_bound && lim > 0)
             per_cu = std::min(per_cu, std::max(1, lim / hrms1d_tile_outputs(a->variant, shape)));
