@@ -444,7 +444,8 @@ Shape1D default_shape(int variant, int dtype)
 {
     // measured on the 1000 x 2^21, Hmax = 32 batch
     if (variant == HRMS_EQ1) return Shape1D{512, 8, 0, 0};
-    if (variant == HRMS_MAX) return Shape1D{256, 8, 0, 0};
+    if (variant == HRMS_MAX)   // FP32: the top band in a window-form launch of its own
+        return dtype == HRMS_F32 ? Shape1D{256, 8, 0, 32} : Shape1D{256, 8, 0, 0};
     if (variant == HRMS_GREEDY)   // 2-byte bins halve the lines: more outputs per workgroup pay
         return dtype == HRMS_F32 ? Shape1D{256, 8, 0, 0} : Shape1D{512, 8, 0, 0};
     if (variant == HRMS_OPT) return kOptShape;
@@ -490,12 +491,13 @@ int plan_host_1d(hrms_ctx* c, const hrms_run1d_args* a, const Shape1D& shape, Pl
     // tiles most expensive first. For eq. (2)-(4) tiles are cut inside bands
     // and a tile's cost is the positions it stages plus the terms it adds;
     // with shape.top set, the bands whose top level is at least shape.top go
-    // to a second launch of the LDS form (kTopShape). Tile lists depend only
+    // to a second launch (hrms1d_top_shape). Tile lists depend only
     // on (length, levels, alignment) and are shared by the spectra that agree
     // on them.
     const bool eq1 = a->variant == HRMS_EQ1;
     const int T = hrms1d_tile_outputs(a->variant, shape);
-    const int Ttop = hrms1d_tile_outputs(a->variant, kTopShape);
+    const Shape1D tshape = hrms1d_top_shape(a->variant);
+    const int Ttop = hrms1d_top_tile(a->variant);
     const int vec = 16 / dtype_bytes(a->dtype);
     const int nq = (c->cu_count >= kMaxQueues && c->cu_count % kMaxQueues == 0) ? kMaxQueues : 1;
     struct Geo {
@@ -537,7 +539,7 @@ int plan_host_1d(hrms_ctx* c, const hrms_run1d_args* a, const Shape1D& shape, Pl
                     const int lo = l + 1 < g.nlev ? (n >> (l + 1)) : 0;
                     const int ht = 1 << l;
                     const bool top = shape.top > 0 && ht >= shape.top;
-                    const Shape1D& sh = top ? kTopShape : shape;
+                    const Shape1D& sh = top ? tshape : shape;
                     const int tt = top ? Ttop : hrms1d_band_tile(a->variant, shape, ht, 1 << (g.nlev - 1));
                     const int64_t terms = a->variant == HRMS_MAX || a->variant == HRMS_OPT
                                               ? (int64_t)ht * (ht + 1) / 2
@@ -655,7 +657,7 @@ int plan_host_1d(hrms_ctx* c, const hrms_run1d_args* a, const Shape1D& shape, Pl
         if (tiles.empty()) continue;
         hipError_t oe = hipSuccess;
         int per_cu =
-            hrms1d_max_blocks_per_cu(a->variant, a->dtype, part ? kTopShape : shape, &oe);
+            hrms1d_max_blocks_per_cu(a->variant, a->dtype, part ? hrms1d_top_shape(a->variant) : shape, &oe);
         if (per_cu <= 0)
             return hip_fail(c, oe != hipSuccess ? oe : hipErrorInvalidConfiguration,
                             "occupancy query of the 1D kernel");
@@ -1034,7 +1036,7 @@ hipError_t enqueue_1d(const hrms_run1d_args* a, const Plan1D* P, const PlanDev& 
             rp.tiles = D.tiles_top;
             rp.qbeg = D.qbeg_top;
             rp.counters = D.counters + kMaxQueues;
-            if ((e = launch_hrms1d(a->variant, a->dtype, kTopShape, rp, P->grid_top, stream)) !=
+            if ((e = launch_hrms1d(a->variant, a->dtype, hrms1d_top_shape(a->variant), rp, P->grid_top, stream)) !=
                 hipSuccess)
                 return e;
         }

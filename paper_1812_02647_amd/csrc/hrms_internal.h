@@ -122,11 +122,22 @@ struct Shape1D {
     int chunk;     // eq. (2)-(4): positions per LDS chunk (two are kept); 0: gathered
                    // from global memory (and eq. (1))
     int top;       // eq. (2)-(4): bands whose top level is at least `top` run in a
-                   // second launch of the LDS form with kTopShape; 0: none
+                   // second launch (hrms1d_top_shape); 0: none
 };
 
 // Launch shape of the LDS form for the top bands of a split launch.
 constexpr Shape1D kTopShape{1024, 8, 16384, 0};
+// eq. (2)'s top bands run in the window form instead, one run of WG outputs
+// per tile: an XCD's resident workgroups then share one spectrum's top band
+// and walk its harmonics at about the same pace, so that the lines harmonic
+// k + 1 reads are still in the L2 from harmonic k of other workgroups.
+constexpr Shape1D kTopWinShape{256, 8, 0, 0};
+inline Shape1D hrms1d_top_shape(int variant) { return variant == 1 ? kTopWinShape : kTopShape; }
+// Outputs per tile of the split launch.
+inline int hrms1d_top_tile(int variant)
+{
+    return variant == 1 ? kTopWinShape.wg : kTopShape.wg * kTopShape.r;
+}
 // The exhaustive-path sum's only launch shape: 256 lanes, 8 outputs per lane
 // taken in sequence, bins read straight from memory.
 constexpr Shape1D kOptShape{256, 8, 0, 0};
