@@ -295,7 +295,8 @@ int hrms_run_1d_noalloc(hrms_handle h, const hrms_run1d_args* a, void* hip_strea
 
 /* Picks the fastest compiled launch shape (threads per workgroup, outputs per
  * thread, LDS chunk or 0 for the gathered form, and the lowest top level of the
- * bands handed to a second launch of the LDS form, 0 for none) for batches
+ * bands handed to a second launch, 0 for none: eq. (2) runs them in the window
+ * form, eq. (3)-(4) in the LDS form) for batches
  * like `a` -- same variant, storage type, largest
  * Hmax and mean spectrum length within a factor of two -- by timing `reps` runs
  * of each shape on `hip_stream` (the call blocks until they finish). Later
