@@ -13,9 +13,11 @@ of the four variants (standard eq. (1), Max, freq-bin, Greedy). value = input
 bins of the batch / step time.
 
 The JSON line also carries:
-  roofline      -- the dominant kernel (the variant with the longest launch):
-                   algorithmic bytes per launch / its mean launch time (HIP
-                   events on the launch stream) against the 8 TB/s HBM peak;
+  roofline      -- the dominant kernel (the longest launch: a variant's time
+                   over its number of harmonic-sum launches, which
+                   hrms_plan_1d gives): algorithmic bytes per launch / its
+                   mean launch time (HIP events on the launch stream) against
+                   the 8 TB/s HBM peak;
   cpu_baseline  -- the CPU oracle (as it stands) on a bounded sample of the
                    same batch, one spectrum per thread on the host cores;
   per_variant   -- every variant's launch time, G bins/s and HBM fraction;
@@ -50,7 +52,7 @@ METRIC = "G input bins/s and % of HBM peak, 1D batch Hmax=32, FP32 vs FP16-stora
 HBM_PEAK_GBS = 8000.0
 VARIANT_NAMES = ["eq1", "max", "freqbin", "greedy"]
 # kernels of the default launch shapes
-KERNEL_OF = {"eq1": "k_hrms1d_eq1", "max": "k_hrms1d_win", "freqbin": "k_hrms1d_gather+k_hrms1d_span",
+KERNEL_OF = {"eq1": "k_hrms1d_eq1", "max": "k_hrms1d_win", "freqbin": "k_hrms1d_gather",
              "greedy": "k_hrms1d_gather"}
 
 
@@ -104,9 +106,11 @@ def measured_traffic(workload: str, variant: str, dtype: str = "f32"):
     return None
 
 
-def alg_bytes_per_launch(total_bins: int, h_floats: int, in_bytes: int) -> int:
-    """Compulsory HBM bytes of one harmonic-sum launch over a batch: each input
-    bin read once, each output written once (h planes, max-SNR, best-H)."""
+def alg_bytes_per_pass(total_bins: int, h_floats: int, in_bytes: int) -> int:
+    """Compulsory HBM bytes of one variant's harmonic sum over a batch (all its
+    launches): each input bin read once, each output written once (h planes,
+    max-SNR, best-H). Per launch of a split variant: the same rate, as bytes
+    and time both divide by its launches."""
     return total_bins * in_bytes + 4 * h_floats + 4 * total_bins + 1 * total_bins
 
 
@@ -222,10 +226,14 @@ class Runner:
         per = {}
         for k, v in enumerate(self.variants):
             t = float(np.mean([e[1 + k].elapsed_time(e[2 + k]) for e in ev]))
-            byts = alg_bytes_per_launch(self.total, self.layouts[v], self.in_bytes)
+            byts = alg_bytes_per_pass(self.total, self.layouts[v], self.in_bytes)
             name = VARIANT_NAMES[v]
+            shape, launches = self.H.hrms_plan_1d(self.handle, self.run_args[v])
             per[name] = {
                 "ms": round(t, 4),
+                "launches": launches,
+                "mean_launch_ms": round(t / max(1, launches), 4),
+                "shape": list(shape),
                 "gbins_per_s": round(self.total / (t * 1e-3) / 1e9, 2),
                 "alg_bytes": byts,
                 "achieved_gbs": round(byts / (t * 1e-3) / 1e9, 1),
@@ -429,7 +437,7 @@ def workload_batch(args):
     copy_gbs = copy_ceiling(xd)
     for v in per_variant.values():
         v["frac_copy"] = round(v["achieved_gbs"] / copy_gbs, 4)
-    dom = max(per_variant, key=lambda k: per_variant[k]["ms"])
+    dom = max(per_variant, key=lambda k: per_variant[k]["mean_launch_ms"])
     d = per_variant[dom]
     del r32
     torch.cuda.empty_cache()
@@ -512,6 +520,8 @@ def workload_batch(args):
         "roofline": {
             "bound": "hbm",
             "kernel": f"{KERNEL_OF[dom]} ({dom})",
+            "launches_per_step": d["launches"],
+            "mean_launch_ms": d["mean_launch_ms"],
             "achieved": d["achieved_gbs"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

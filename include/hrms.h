@@ -308,6 +308,17 @@ int hrms_run_1d_noalloc(hrms_handle h, const hrms_run1d_args* a, void* hip_strea
 int hrms_autotune_1d(hrms_handle h, const hrms_run1d_args* a, void* hip_stream, int reps,
                      int32_t* chosen);
 
+/* The launches hrms_run_1d would make for `a` on this handle, without running
+ * them. info (host, five entries) receives the launch shape {wg, r, chunk,
+ * top} the run uses (the handle's tuned shape for batches like `a`, else the
+ * one HRMS_FORCE_SHAPE names, else the default) and the number of
+ * harmonic-sum kernel launches: 2 when bands at or above `top` run in a launch
+ * of their own, 1 otherwise, 0 when the batch has no outputs. Builds (or finds
+ * in the handle's cache) the host side of the plan; touches no device memory
+ * and enqueues nothing. Errors: as hrms_run_1d's argument checks, and
+ * HRMS_E_INVAL for a NULL info. */
+int hrms_plan_1d(hrms_handle h, const hrms_run1d_args* a, int32_t* info);
+
 /* Harmonic sum of a 2D plane, HRMS_EQ1 .. HRMS_GREEDY and HRMS_GREEDY_FDOT
  * (HRMS_OPT: HRMS_E_UNSUPPORTED). */
 int hrms_run_2d(hrms_handle h, const hrms_run2d_args* a, void* hip_stream);

@@ -1416,6 +1416,27 @@ int hrms_autotune_1d(hrms_handle h, const hrms_run1d_args* a, void* hip_stream, 
     return HRMS_OK;
 }
 
+int hrms_plan_1d(hrms_handle h, const hrms_run1d_args* a, int32_t* info)
+{
+    if (!h) return fail(nullptr, HRMS_E_INVAL, "handle is NULL");
+    h->err.clear();
+    if (!info) return fail(h, HRMS_E_INVAL, "info is NULL");
+    int st = validate_1d(h, a, true);
+    if (st != HRMS_OK) return st;
+    hipError_t e = hipSetDevice(h->device);
+    if (e != hipSuccess) return hip_fail(h, e, "hipSetDevice");
+    const Shape1D shape = shape_for(h, a);
+    Plan1D* P = nullptr;
+    st = get_plan_1d_host(h, a, shape, &P);
+    if (st != HRMS_OK) return st;
+    info[0] = shape.wg;
+    info[1] = shape.r;
+    info[2] = shape.chunk;
+    info[3] = shape.top;
+    info[4] = (P->tiles.empty() ? 0 : 1) + (P->tiles_top.empty() ? 0 : 1);
+    return HRMS_OK;
+}
+
 int hrms_run_2d(hrms_handle h, const hrms_run2d_args* a, void* hip_stream)
 {
     if (!h) return fail(nullptr, HRMS_E_INVAL, "handle is NULL");

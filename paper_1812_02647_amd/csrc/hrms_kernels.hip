@@ -850,7 +850,7 @@ __global__ __launch_bounds__(WG) void k_hrms1d_gather(const Run1DParams p)
             float acc[R], best[R];
             int st[R], pos[R], nn[R];
             bool act[R];
-    #pragma unroll
+#pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int n = a + r * WG + tid;
                 act[r] = n < aend;
@@ -863,16 +863,16 @@ __global__ __launch_bounds__(WG) void k_hrms1d_gather(const Run1DParams p)
             }
             for (int i = 1; i <= ht; ++i) {
                 float tv[R];
-    #pragma unroll
+#pragma unroll
                 for (int r = 0; r < R; ++r) pos[r] += nn[r];
                 if constexpr (VAR == kFreqbin) {
-    #pragma unroll
+#pragma unroll
                     for (int r = 0; r < R; ++r) tv[r] = buffer_elem<DT>(rs, pos[r]);
                 } else if constexpr (VAR == kMax) {
-    #pragma unroll
+#pragma unroll
                     for (int r = 0; r < R; ++r) tv[r] = buffer_elem<DT>(rs, pos[r]);
                     for (int jj = 1; jj < i; ++jj) {
-    #pragma unroll
+#pragma unroll
                         for (int r = 0; r < R; ++r) {
                             const float w = buffer_elem<DT>(rs, pos[r] + jj);
                             tv[r] = w > tv[r] ? w : tv[r];
@@ -880,17 +880,17 @@ __global__ __launch_bounds__(WG) void k_hrms1d_gather(const Run1DParams p)
                     }
                 } else {
                     if (i == 1) {
-    #pragma unroll
+#pragma unroll
                         for (int r = 0; r < R; ++r) tv[r] = buffer_elem<DT>(rs, pos[r]);
                     } else {
                         float x0[R], x1[R];
-    #pragma unroll
+#pragma unroll
                         for (int r = 0; r < R; ++r) {
                             const int q = pos[r] + (st[r] >> 8);
                             x0[r] = buffer_elem<DT>(rs, q);
                             x1[r] = buffer_elem<DT>(rs, q + 1);
                         }
-    #pragma unroll
+#pragma unroll
                         for (int r = 0; r < R; ++r) {
                             const bool step = x1[r] > x0[r];
                             tv[r] = step ? x1[r] : x0[r];
@@ -898,7 +898,7 @@ __global__ __launch_bounds__(WG) void k_hrms1d_gather(const Run1DParams p)
                         }
                     }
                 }
-    #pragma unroll
+#pragma unroll
                 for (int r = 0; r < R; ++r) acc[r] = acc[r] + tv[r];
                 if ((i & (i - 1)) == 0) {
                     const int li = __builtin_ctz((unsigned)i);
@@ -911,7 +911,7 @@ __global__ __launch_bounds__(WG) void k_hrms1d_gather(const Run1DParams p)
                                   (uint32_t)__builtin_amdgcn_readlane(lho_lo, li));
                     const __amdgpu_buffer_rsrc_t hrs = out_rsrc(p.h + ho + a, tn * 4);
                     const bool fin = i == ht;
-    #pragma unroll
+#pragma unroll
                     for (int r = 0; r < R; ++r) {
                         const float hv = acc[r] * rh;
                         const float snr = (hv - m0) * q0;

@@ -34,8 +34,8 @@ VARIANTS = {"eq1": HRMS_EQ1, "max": HRMS_MAX, "freqbin": HRMS_FREQBIN, "greedy":
 DTYPES = {"f32": HRMS_F32, "f16": HRMS_F16, "bf16": HRMS_BF16}
 
 EXPORTED = ["hrms_create", "hrms_destroy", "hrms_layout_1d", "hrms_layout_2d", "hrms_run_1d",
-            "hrms_run_1d_noalloc", "hrms_autotune_1d", "hrms_run_2d", "hrms_quantize", "hrms_strerror",
-            "hrms_last_error"]
+            "hrms_run_1d_noalloc", "hrms_autotune_1d", "hrms_plan_1d", "hrms_run_2d", "hrms_quantize",
+            "hrms_strerror", "hrms_last_error"]
 
 
 class hrms_run1d_args(C.Structure):
@@ -141,6 +141,8 @@ def lib():
         L.hrms_autotune_1d.argtypes = [vp, C.POINTER(hrms_run1d_args), vp, i32,
                                        C.POINTER(C.c_int32)]
         L.hrms_autotune_1d.restype = i32
+        L.hrms_plan_1d.argtypes = [vp, C.POINTER(hrms_run1d_args), C.POINTER(C.c_int32)]
+        L.hrms_plan_1d.restype = i32
         L.hrms_run_2d.argtypes = [vp, C.POINTER(hrms_run2d_args), vp]
         L.hrms_run_2d.restype = i32
         L.hrms_quantize.argtypes = [vp, C.POINTER(hrms_quantize_args), vp]
@@ -211,6 +213,14 @@ def hrms_autotune_1d(handle, args: hrms_run1d_args, stream=None, reps: int = 3):
     _check(lib().hrms_autotune_1d(handle, C.byref(args), _stream_ptr(stream), reps, chosen),
            handle)
     return tuple(chosen)
+
+
+def hrms_plan_1d(handle, args: hrms_run1d_args):
+    """The launches hrms_run_1d would make for this batch:
+    ((wg, r, chunk, top), number of harmonic-sum launches)."""
+    info = (C.c_int32 * 5)()
+    _check(lib().hrms_plan_1d(handle, C.byref(args), info), handle)
+    return tuple(info[:4]), int(info[4])
 
 
 def hrms_run_2d(handle, args: hrms_run2d_args, stream=None) -> None:

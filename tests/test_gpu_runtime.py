@@ -97,6 +97,38 @@ def test_autotune_and_tune_cache(tmp_path):
         H.hrms_destroy(h)
 
 
+def test_plan_query_reports_the_run_shape_and_launches(monkeypatch):
+    """hrms_plan_1d names the shape a run uses and its harmonic-sum launches:
+    two for eq. (2) on FP32 with a band at level 32 (that band runs in a
+    launch of its own), one otherwise, and the forced shape when
+    HRMS_FORCE_SHAPE names one; the query enqueues nothing."""
+    import torch
+    from paper_1812_02647_amd import hrms as H
+    x, offsets, _ = synth.batch(3, [1 << 17, 70001, 4096], seed=31)
+    xd, _ = to_device_input(x, "f32")
+    monkeypatch.delenv("HRMS_FORCE_SHAPE", raising=False)
+    h = make_handle()
+    try:
+        case_log("plan query: default shapes")
+        b = H.Batch1D(xd, offsets, 1, 32)
+        b.max_snr.fill_(float("nan"))
+        shape, n = H.hrms_plan_1d(h, b.args)
+        assert shape[3] == 32 and n == 2
+        torch.cuda.synchronize()
+        assert torch.isnan(b.max_snr).all()          # nothing ran
+        shape, n = H.hrms_plan_1d(h, H.Batch1D(xd, offsets, 1, 16).args)
+        assert n == 1                                # no band at level 32
+        for v in (0, 2, 3):
+            shape, n = H.hrms_plan_1d(h, H.Batch1D(xd, offsets, v, 32).args)
+            assert shape[3] == 0 and n == 1, (v, shape, n)
+        case_log("plan query: forced shape")
+        monkeypatch.setenv("HRMS_FORCE_SHAPE", "512:8:0:32")
+        shape, n = H.hrms_plan_1d(h, H.Batch1D(xd, offsets, 2, 32).args)
+        assert shape == (512, 8, 0, 32) and n == 2
+    finally:
+        H.hrms_destroy(h)
+
+
 # every launch shape compiled into the library, forced in turn: wg:r:chunk:top
 FUND_SHAPES = ["1024:8:16384:0", "1024:16:16384:0", "512:8:8192:0", "256:8:0:0", "256:8:0:32",
                "256:16:0:0", "512:8:0:0", "512:8:0:32"]
