@@ -45,6 +45,10 @@ def test_strerror_and_null_handles():
     a = H.hrms_run1d_args()
     assert H.lib().hrms_run_1d(None, C.byref(a), None) == H.HRMS_E_INVAL
     assert "handle" in H.last_error(None)
+    info = (C.c_int32 * 5)(*([-7] * 5))
+    assert H.lib().hrms_plan_1d(None, C.byref(a), info) == H.HRMS_E_INVAL
+    assert "handle" in H.last_error(None)
+    assert list(info) == [-7] * 5   # nothing written on error
 
 
 def test_create_without_device_reports_nodevice():
