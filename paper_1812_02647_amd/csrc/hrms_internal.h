@@ -154,8 +154,9 @@ inline int hrms1d_tile_outputs(int variant, const Shape1D& s)
     return s.wg * s.r;
 }
 // eq. (2) and the exhaustive-path sum in the gathered shapes run the window
-// form, whose lanes walk a tile's outputs in sequence: a tile may hold any
-// multiple of wg * 4 outputs.
+// form, whose lanes walk a tile's outputs in sequence (wg * 4 or wg * 2 at a
+// time in the cheap bands, wg in the deep ones), so a tile may hold any
+// number of outputs.
 inline bool hrms1d_window_form(int variant, const Shape1D& s)
 {
     return (variant == 1 || variant == 4) && s.chunk == 0;
