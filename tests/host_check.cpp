@@ -105,7 +105,17 @@ static void check_plan(hrms_ctx* c, const hrms_run1d_args* a, const Shape1D& sha
                           t.a, t.aend, l, N);
                     const bool top = shape.top > 0 && (1 << l) >= shape.top;
                     CHECK(top == (part == 1), "band %d in launch %d\n", l, part);
+                    // tile length: the band's (cheap bands of the forms without
+                    // LDS staging take several runs) or the split launch's
+                    const int cap = part ? hrms1d_top_tile(a->variant)
+                                         : hrms1d_band_tile(a->variant, shape, 1 << l,
+                                                            1 << (nlev - 1));
+                    CHECK(t.aend - t.a <= cap, "tile of %d outputs in band %d (at most %d)\n",
+                          t.aend - t.a, l, cap);
                 }
+                if (a->variant == HRMS_EQ1)
+                    CHECK(t.aend - t.a <= hrms1d_tile_outputs(a->variant, shape),
+                          "eq1 tile of %d outputs\n", t.aend - t.a);
                 for (int n = t.a; n < t.aend; ++n) seen[(size_t)n]++;
             }
         }
