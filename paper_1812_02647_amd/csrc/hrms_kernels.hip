@@ -790,6 +790,283 @@ __global__ __launch_bounds__(WG) void k_hrms1d_eq1(const Run1DParams p)
 }
 
 // --------------------------------------------------------------------------
+// eq. (1), LDS-staged. The tile's outputs are taken WG at a time (a run); for
+// a run starting at output ns, term k of its outputs reads the contiguous
+// positions round(n k / Lh), n = ns .. ns + WG - 1, at most S k + 1 of them
+// (S = WG / Lh). Each run's Lh spans are copied into LDS with aligned 16-byte
+// loads, one vector per lane, and the terms are then read from LDS; the next
+// run's vectors are loaded into registers while the current one is summed.
+// The terms, the order of the adds and the outputs are those of the direct
+// form above; only where a bin is read from differs.
+//
+// LDS layout of one run: span k (k = 1..Lh) holds S k / V + 1 vectors of V
+// elements starting at the V-aligned position below its first bin, at float
+// offset o_k = S k (k - 1) / 2 + V (k - 1). Spans k and Lh + 1 - k together
+// hold S (Lh + 1) / V + 2 vectors, so a flat vector index maps to its span
+// with one division.
+// --------------------------------------------------------------------------
+// Workgroup barrier for data exchanged through LDS only: waits for this
+// wave's LDS operations (lgkmcnt 0; vmcnt and expcnt left at their maximum in
+// the gfx9 encoding) and not for its global loads and stores, so loads issued
+// ahead of the barrier stay in flight. The empty asm statements keep the
+// compiler from moving memory accesses across it.
+__device__ __forceinline__ void lds_barrier()
+{
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+template <int DT, int WG>
+struct Eq1Lds {
+    static constexpr int V = Elem<DT>::kVec;
+    static constexpr int kHmax = 1 << (kMaxLevels - 1);
+    // floats of one run's staging at Lh = kHmax (the largest over Lh)
+    static constexpr int kFloats = WG * (kHmax + 1) / 2 + V * kHmax;
+    // vectors per thread per run at most
+    static constexpr int kQ = (WG * (kHmax + 1) / (2 * V) + kHmax + WG - 1) / WG;
+    static_assert(WG % kHmax == 0, "S = WG / Lh must be a whole multiple of V");
+    static_assert((WG / kHmax) % V == 0, "S = WG / Lh must be a whole multiple of V");
+};
+
+// (at most 128 VGPRs: two 512-thread workgroups per CU, as the LDS allows)
+template <int DT, int WG, int R, bool CAND>
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4)))
+void k_hrms1d_eq1_lds(const Run1DParams p)
+{
+    using L = Eq1Lds<DT, WG>;
+    constexpr int V = L::V;
+    constexpr int B = Elem<DT>::kBytes;
+    const int tid = (int)threadIdx.x;
+    __shared__ int s_claim[2];
+    __shared__ CandStage cands;
+    // (plus one vector of pad that lanes without a vector write to)
+    __shared__ __attribute__((aligned(16))) float stage[2][L::kFloats + 8];
+    int cq = (int)(blockIdx.x % (unsigned)p.nqueues), visited = 0;
+    if (tid == 0) {
+        s_claim[0] = claim_tile(p, cq, visited);
+        cands.n = 0u;
+    }
+    __syncthreads();
+    int t = uniform(s_claim[0]);
+    for (int c = 0; t >= 0; ++c) {
+        if (tid == 0) s_claim[(c + 1) & 1] = claim_tile(p, cq, visited);
+        const TileRec ct = ldc(p.tiles + t);
+        const int a = ct.a;
+        const int N = ct.n;
+        const int nl = ct.nlev;
+        const int aend = ct.aend;
+        const int sh = nl - 1;
+        const int Lh = 1 << sh;
+        const unsigned half = (unsigned)Lh >> 1;
+        const int S = WG >> sh;
+        // vectors of one run, and of a pair of spans k, Lh + 1 - k
+        const int Qt = (S * Lh * (Lh + 1) / 2) / V + Lh;
+        const int Pq = S * (Lh + 1) / V + 2;
+        // resource from the V-aligned element at or below the spectrum's
+        // first bin: vectors then fall on 16-byte boundaries of the batch.
+        // Its range ends at the 16-byte block holding the spectrum's last bin
+        // (the range check acts per dword, and a 2-byte bin may share its
+        // dword with the next spectrum); x's 16-byte alignment keeps that
+        // block mapped. Positions past the spectrum's end are used only by
+        // outputs past the tile's end, whose stores are discarded.
+        const int d = (int)(ct.xoff & (int64_t)(V - 1));
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)(static_cast<const char*>(p.x) + (ct.xoff - d) * B), (short)0,
+            ((N + d) * B + 15) & ~15, kBufferFlags);
+        const int tn = aend - a;
+        const int runs = (tn + WG - 1) / WG < R ? (tn + WG - 1) / WG : R;
+
+        // Span layout of the tile's runs: the same for every run, since
+        // run ns + WG reads every span S k positions (a whole number of
+        // vectors) further on. Vector j of this thread: LDS float offset lo,
+        // byte offset ga in the resource for the next run to load, and the
+        // step sk between runs. A lane without a vector loads the resource's
+        // first one and writes it to the pad: no lane takes a branch around
+        // its loads, which would make the compiler wait for every load in
+        // flight (the next runs' too) before each LDS write.
+        int lo[L::kQ], ga[L::kQ], sk[L::kQ];
+        {
+            // q / Pq by a multiply: exact for q Pq < 2^32
+            const unsigned mg = Lh == 1 ? 0u : 0xffffffffu / (unsigned)Pq + 1u;
+#pragma unroll
+            for (int j = 0; j < L::kQ; ++j) {
+                const int q = tid + j * WG;
+                int k = 1, off = q;
+                if (Lh > 1) {
+                    const int pr = (int)__umulhi((unsigned)q, mg);
+                    const int w = q - pr * Pq;
+                    const int c1 = S * (pr + 1) / V + 1;
+                    k = w < c1 ? pr + 1 : Lh - pr;
+                    off = w < c1 ? w : w - c1;
+                }
+                const int first = (int)(((unsigned)a * (unsigned)k + half) >> sh);
+                const bool has = q < Qt;
+                lo[j] = has ? S * k * (k - 1) / 2 + V * (k - 1) + off * V : L::kFloats;
+                ga[j] = has ? (((d + first) & ~(V - 1)) + off * V) * B : 0;
+                sk[j] = has ? S * k * B : 0;
+            }
+        }
+        // vectors of the next run to load into registers
+        auto load_run = [&](uint4 (&v)[L::kQ]) {
+#pragma unroll
+            for (int j = 0; j < L::kQ; ++j) {
+                const auto r4 = __builtin_amdgcn_raw_buffer_load_b128(rs, ga[j], 0, 0);
+                v[j] = make_uint4(r4[0], r4[1], r4[2], r4[3]);
+                ga[j] += sk[j];
+            }
+        };
+        auto store_run = [&](const uint4 (&v)[L::kQ], float* buf) {
+#pragma unroll
+            for (int j = 0; j < L::kQ; ++j) {
+                if constexpr (DT == kF32) {
+                    *reinterpret_cast<uint4*>(buf + lo[j]) = v[j];
+                } else {
+                    const uint32_t w4[4] = {v[j].x, v[j].y, v[j].z, v[j].w};
+                    float f[8];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        f[2 * e] = DT == kF16 ? h2f(w4[e] & 0xffffu) : bf2f(w4[e] & 0xffffu);
+                        f[2 * e + 1] = DT == kF16 ? h2f(w4[e] >> 16) : bf2f(w4[e] >> 16);
+                    }
+                    *reinterpret_cast<float4*>(buf + lo[j]) = make_float4(f[0], f[1], f[2], f[3]);
+                    *reinterpret_cast<float4*>(buf + lo[j] + 4) = make_float4(f[4], f[5], f[6], f[7]);
+                }
+            }
+        };
+
+        // At Lh = kHmax (every tile of a spectrum summed to H = 32), the LDS
+        // byte offset of each term is kept per thread for the whole tile:
+        // term k of output n + r WG sits where term k of output n sits in
+        // run 0. Offsets are below 2^16 (one buffer), two to a register.
+        constexpr int kH = L::kHmax;
+        static_assert(L::kFloats * 4 < 65536, "term offsets are 16-bit");
+        unsigned ix2[kH / 2];
+        if (Lh == kH) {
+            int o = 0;
+#pragma unroll
+            for (int k = 1; k <= kH; ++k) {
+                const unsigned pk = (unsigned)(a + tid) * (unsigned)k + half;
+                const unsigned pa = (unsigned)a * (unsigned)k + half;
+                const unsigned bo =
+                    (unsigned)(o - ((d + (int)(pa >> sh)) & ~(V - 1)) + d + (int)(pk >> sh)) * 4u;
+                if (k & 1)
+                    ix2[(k - 1) / 2] = bo;
+                else
+                    ix2[(k - 1) / 2] |= bo << 16;
+                o += S * k + V;
+            }
+        }
+
+        // Run r is summed from stage[r & 1]; the registers hold the two runs
+        // after it, so each run's loads have two runs' time to arrive.
+        // term k of output n of a run: LDS float o_k + (d + pos(n, k)) -
+        // base_k, base_k the aligned position below span k's first bin; the
+        // same for every run, so it is taken at the tile's first run
+        auto sum_run = [&](int r, uint4 (&vn)[L::kQ]) {
+            const float* buf = stage[r & 1];
+            const unsigned n0 = (unsigned)(a + tid);
+            const int n = a + r * WG + tid;
+            // acc[m] is level sh - m: term k belongs to the levels
+            // m <= tz(k), so with k = 1 mod 4 only the fourth term of a group
+            // has a level set known at run time
+            float acc[kMaxLevels];
+#pragma unroll
+            for (int m = 0; m < kMaxLevels; ++m) acc[m] = 0.0f;
+            unsigned tk = half, tks = half;
+            int ok = 0;
+            auto term = [&](int k) {
+                tk += n0;
+                tks += (unsigned)a;
+                const int bk = (d + (int)(tks >> sh)) & ~(V - 1);
+                const float val = buf[ok - bk + d + (int)(tk >> sh)];
+                ok += S * k + V;
+                return val;
+            };
+            auto add_to = [&](float tv, int tz) {
+#pragma unroll
+                for (int m = 0; m < kMaxLevels; ++m)
+                    if (m <= tz) acc[m] = acc[m] + tv;
+            };
+            if (Lh == kH) {
+                // every term's level set known at compile time
+#pragma unroll
+                for (int k0 = 1; k0 <= kH; k0 += 8) {
+                    float tv[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const unsigned w = ix2[(k0 - 1 + u) / 2];
+                        const unsigned bo = (u & 1) ? w >> 16 : w & 0xffffu;
+                        tv[u] = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(buf) + bo);
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) add_to(tv[u], __builtin_ctz((unsigned)(k0 + u)));
+                }
+            } else if (Lh >= 4) {
+                for (int k = 1; k <= Lh; k += 4) {
+                    const float t0 = term(k), t1 = term(k + 1), t2 = term(k + 2), t3 = term(k + 3);
+                    add_to(t0, 0);
+                    add_to(t1, 1);
+                    add_to(t2, 0);
+                    add_to(t3, 2 + __builtin_ctz((unsigned)(k + 3) >> 2));   // k + 3 = 0 mod 4
+                }
+            } else {
+                for (int k = 1; k <= Lh; ++k) add_to(term(k), __builtin_ctz((unsigned)k));
+            }
+
+            float best = 0.0f;
+            int bl = 0;
+            // levels l = sh - m in increasing order (the first of equal SNRs
+            // is kept)
+#pragma unroll
+            for (int m = kMaxLevels - 1; m >= 0; --m) {
+                const int l = sh - m;
+                const bool lv = l >= 0;
+                const LevelConst cst = ldc(p.consts + (int64_t)ct.spec * kMaxLevels + (lv ? l : 0));
+                const int64_t ho = lv ? ldc(p.spec[ct.spec].hoff + l) : 0;
+                const __amdgpu_buffer_rsrc_t hrs =
+                    out_rsrc(p.h + ho + a, lv && (p.out_mask & 1u) ? tn * 4 : 0);
+                const float hv = acc[m] * cst.rh;
+                stream_store_b32(__float_as_uint(hv), hrs, tid * 4, r * WG * 4);
+                const float snr = (hv - cst.m) * cst.q;
+                if (lv && (l == 0 || snr > best)) {
+                    best = snr;
+                    bl = l;
+                }
+            }
+            const __amdgpu_buffer_rsrc_t mrs =
+                out_rsrc(p.max_snr + ct.xoff + a, (p.out_mask & 2u) ? tn * 4 : 0);
+            const __amdgpu_buffer_rsrc_t brs = out_rsrc(p.best_h + ct.xoff + a, (p.out_mask & 4u) ? tn : 0);
+            stream_store_b32(__float_as_uint(best), mrs, tid * 4, r * WG * 4);
+            stream_store_b8((uint8_t)(1u << bl), brs, tid, r * WG);
+            if constexpr (CAND)
+                append_candidates(p, cands, n < aend && best >= p.cand_thr, ct.spec, n, best, 1 << bl);
+            // run r + 1 into the other buffer, last read before the previous
+            // barrier; then its registers take run r + 3 (runs past the
+            // tile's end are loaded and summed too, and their stores
+            // discarded)
+            store_run(vn, stage[(r + 1) & 1]);
+            lds_barrier();
+            load_run(vn);
+        };
+
+        uint4 v0[L::kQ], v1[L::kQ];
+        load_run(v0);
+        store_run(v0, stage[0]);
+        load_run(v0);
+        load_run(v1);
+        lds_barrier();
+        for (int r = 0; r < runs; r += 2) {
+            sum_run(r, v0);
+            sum_run(r + 1, v1);
+        }
+        if constexpr (CAND) flush_candidates(p, cands, WG);
+        t = uniform(s_claim[(c + 1) & 1]);
+    }
+}
+
+// --------------------------------------------------------------------------
 // eq. (2)-(4), gathered straight from global memory: a tile is a run of
 // outputs of one band, taken WG * R at a time (a tile of a cheap band holds
 // several such runs); thread t holds outputs a + r WG + t of the current run
@@ -1736,7 +2013,11 @@ void* fund_kernel()
 template <int DT, int WG, int R, int C, bool CAND>
 void* eq1_kernel()
 {
-    return reinterpret_cast<void*>(&k_hrms1d_eq1<DT, WG, R, C, CAND>);
+    // chunk 1 marks the LDS-staged form
+    if constexpr (C == 1)
+        return reinterpret_cast<void*>(&k_hrms1d_eq1_lds<DT, WG, R, CAND>);
+    else
+        return reinterpret_cast<void*>(&k_hrms1d_eq1<DT, WG, R, C, CAND>);
 }
 
 // Launch shapes compiled into the library: (threads, outputs per thread, LDS
@@ -1798,6 +2079,7 @@ const ShapeEntry kShapes[] = {
     eq1_shape<256, 8, 0>(),
     eq1_shape<256, 4, 0>(),
     eq1_shape<512, 8, 0>(),
+    eq1_shape<512, 8, 1>(),
 };
 
 const ShapeEntry* find_shape(int variant, const Shape1D& s)

@@ -132,7 +132,7 @@ def test_plan_query_reports_the_run_shape_and_launches(monkeypatch):
 # every launch shape compiled into the library, forced in turn: wg:r:chunk:top
 FUND_SHAPES = ["1024:8:16384:0", "1024:16:16384:0", "512:8:8192:0", "256:8:0:0", "256:8:0:32",
                "256:16:0:0", "512:8:0:0", "512:8:0:32"]
-EQ1_SHAPES = ["256:8:0:0", "256:4:0:0", "512:8:0:0"]
+EQ1_SHAPES = ["256:8:0:0", "256:4:0:0", "512:8:0:0", "512:8:1:0"]
 
 
 @pytest.mark.parametrize("variant,shape", [(v, s) for v in [1, 2, 3] for s in FUND_SHAPES] +
@@ -157,6 +157,31 @@ def test_every_launch_shape_matches_oracle(monkeypatch, variant, shape):
         for s in range(len(lengths)):
             check_spectrum(b, out, seen, s, variant, int(hmax[s]), check_f64=False,
                            label=f"shape {shape}")
+    finally:
+        H.hrms_destroy(h)
+
+
+@pytest.mark.parametrize("dtype", ["f16", "bf16", "f32"])
+def test_eq1_lds_form_matches_oracle(monkeypatch, dtype):
+    """eq. (1) in its LDS-staged form (shape 512:8:1) on 2-byte and FP32
+    storage: spectra starting at every residue of the 16-byte vector, tiles
+    ending mid-run, Hmax 1..32; every output equals the oracle's bits."""
+    import torch
+    from paper_1812_02647_amd import hrms as H
+    monkeypatch.setenv("HRMS_FORCE_SHAPE", "512:8:1:0")
+    lengths = [5001, 1, 7, 4099, 513, 12289, 2, 4096, 3]
+    hmax = np.array([32, 1, 2, 4, 8, 16, 32, 32, 32], np.uint8)
+    x, offsets, _ = synth.batch(len(lengths), lengths, seed=41, comb_fraction=0.5)
+    xd, seen = to_device_input(x, dtype)
+    h = make_handle()
+    try:
+        case_log(f"eq1 LDS form dtype={dtype}")
+        b = H.Batch1D(xd, offsets, 0, hmax).run(h)
+        torch.cuda.synchronize()
+        out = fetch(b)
+        for s in range(len(lengths)):
+            check_spectrum(b, out, seen, s, 0, int(hmax[s]), idx=np.arange(lengths[s]),
+                           check_f64=False, label=f"eq1 lds {dtype}")
     finally:
         H.hrms_destroy(h)
 
