@@ -711,14 +711,17 @@ __global__ __launch_bounds__(WG) void k_hrms1d_eq1(const Run1DParams p)
                 }
 #pragma unroll
                 for (int u = 0; u < kEq1Unroll; ++u) {
-                    // k = 1 mod kEq1Unroll, so tz(k + u) = tz(u + 1) but for the last u
-                    const int tz = u + 1 < kEq1Unroll ? __builtin_ctz((unsigned)(u + 1))
-                                                      : __builtin_ctz((unsigned)(k + u));
+                    // k = 1 mod kEq1Unroll, so tz(k + u) = tz(u + 1) but for the
+                    // last u, where it is at least tz(kEq1Unroll)
+                    constexpr int kTz = __builtin_ctz((unsigned)kEq1Unroll);
+                    const int tz = u + 1 < kEq1Unroll
+                                       ? __builtin_ctz((unsigned)(u + 1))
+                                       : kTz + __builtin_ctz((unsigned)(k + u) >> kTz);
 #pragma unroll
-                    for (int l = 0; l < kMaxLevels; ++l) {
-                        if (l >= sh - tz && l < nl) {
+                    for (int m = 0; m < kMaxLevels; ++m) {
+                        if (m <= tz) {
 #pragma unroll
-                            for (int r = 0; r < R; ++r) acc[r][l] = acc[r][l] + v[u][r];
+                            for (int r = 0; r < R; ++r) acc[r][m] = acc[r][m] + v[u][r];
                         }
                     }
                 }
@@ -727,16 +730,16 @@ __global__ __launch_bounds__(WG) void k_hrms1d_eq1(const Run1DParams p)
             for (int k = 1; k <= Lh; ++k) {
                 tk0 += n0;
                 const unsigned sk = (unsigned)(k * WG);
-                const int lmin = sh - __builtin_ctz((unsigned)k);
+                const int tz = __builtin_ctz((unsigned)k);
                 float v[R];
 #pragma unroll
                 for (int r = 0; r < R; ++r)
                     v[r] = buffer_elem<DT>(rs, (int)((tk0 + (unsigned)r * sk) >> sh));
 #pragma unroll
-                for (int l = 0; l < kMaxLevels; ++l) {
-                    if (l >= lmin && l < nl) {
+                for (int m = 0; m < kMaxLevels; ++m) {
+                    if (m <= tz) {
 #pragma unroll
-                        for (int r = 0; r < R; ++r) acc[r][l] = acc[r][l] + v[r];
+                        for (int r = 0; r < R; ++r) acc[r][m] = acc[r][m] + v[r];
                     }
                 }
             }
@@ -752,15 +755,19 @@ __global__ __launch_bounds__(WG) void k_hrms1d_eq1(const Run1DParams p)
         // stores through resources spanning the tile's outputs: a lane past
         // the tile's end stores out of range, which the resource discards
         const int tn = aend - a;
+        // acc[r][m] holds level l = sh - m (term k belongs to the levels
+        // m <= tz(k)); levels are visited in increasing l, so the first of
+        // equal SNRs is kept
 #pragma unroll
-        for (int l = 0; l < kMaxLevels; ++l) {
-            if (l < nl) {
+        for (int m = kMaxLevels - 1; m >= 0; --m) {
+            const int l = sh - m;
+            if (l >= 0) {
                 const LevelConst c = ldc(p.consts + (int64_t)ct.spec * kMaxLevels + l);
                 const int64_t ho = ldc(p.spec[ct.spec].hoff + l);
                 const __amdgpu_buffer_rsrc_t hrs = out_rsrc(p.h + ho + a, tn * 4);
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    const float hv = acc[r][l] * c.rh;
+                    const float hv = acc[r][m] * c.rh;
                     if (p.out_mask & 1u)
                         stream_store_b32(__float_as_uint(hv), hrs, tid * 4, r * WG * 4);
                     const float snr = (hv - c.m) * c.q;
