@@ -648,6 +648,19 @@ __device__ __forceinline__ float buffer_elem(__amdgpu_buffer_rsrc_t rs, int pos)
 }
 
 
+// Element at byte offset bo of a buffer resource.
+template <int DT>
+__device__ __forceinline__ float buffer_elem_at(__amdgpu_buffer_rsrc_t rs, int bo)
+{
+    if constexpr (DT == kF32) {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, bo, 0, 0));
+    } else if constexpr (DT == kF16) {
+        return h2f(__builtin_amdgcn_raw_buffer_load_b16(rs, bo, 0, 0));
+    } else {
+        return bf2f(__builtin_amdgcn_raw_buffer_load_b16(rs, bo, 0, 0));
+    }
+}
+
 // Terms of eq. (1) whose loads a thread issues together.
 constexpr int kEq1Unroll = 4;
 
@@ -686,6 +699,10 @@ __global__ __launch_bounds__(WG) void k_hrms1d_eq1(const Run1DParams p)
         // and its stores are discarded; n k + Lh/2 < 2^32 for every
         // n < HRMS_MAX_BINS + R WG.
         const unsigned n0 = (unsigned)(a + tid);
+        // WG k is a multiple of Lh, so output r's bin of term k is the
+        // bin of output 0 plus r S k exactly (S = WG / Lh): one shift per
+        // term, one add per output
+        const int S = WG >> sh;
         float acc[R][kMaxLevels];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -701,13 +718,13 @@ __global__ __launch_bounds__(WG) void k_hrms1d_eq1(const Run1DParams p)
 #pragma unroll
                 for (int u = 0; u < kEq1Unroll; ++u) {
                     tk0 += n0;
-                    // a uniform offset per output, kept opaque to the loop
-                    // optimiser (which would otherwise keep R kEq1Unroll running
-                    // positions in vector registers)
-                    const unsigned sk = (unsigned)__builtin_amdgcn_readfirstlane((k + u) * WG);
+                    const int b0 = (int)(tk0 >> sh) * Elem<DT>::kBytes;
+                    // the step between outputs in bytes, uniform, kept opaque
+                    // to the loop optimiser (which would otherwise keep
+                    // R kEq1Unroll running offsets in vector registers)
+                    const int sb = __builtin_amdgcn_readfirstlane(S * (k + u) * Elem<DT>::kBytes);
 #pragma unroll
-                    for (int r = 0; r < R; ++r)
-                        v[u][r] = buffer_elem<DT>(rs, (int)((tk0 + (unsigned)r * sk) >> sh));
+                    for (int r = 0; r < R; ++r) v[u][r] = buffer_elem_at<DT>(rs, b0 + r * sb);
                 }
 #pragma unroll
                 for (int u = 0; u < kEq1Unroll; ++u) {
@@ -729,12 +746,12 @@ __global__ __launch_bounds__(WG) void k_hrms1d_eq1(const Run1DParams p)
         } else {
             for (int k = 1; k <= Lh; ++k) {
                 tk0 += n0;
-                const unsigned sk = (unsigned)(k * WG);
+                const int b0 = (int)(tk0 >> sh) * Elem<DT>::kBytes;
+                const int sb = S * k * Elem<DT>::kBytes;
                 const int tz = __builtin_ctz((unsigned)k);
                 float v[R];
 #pragma unroll
-                for (int r = 0; r < R; ++r)
-                    v[r] = buffer_elem<DT>(rs, (int)((tk0 + (unsigned)r * sk) >> sh));
+                for (int r = 0; r < R; ++r) v[r] = buffer_elem_at<DT>(rs, b0 + r * sb);
 #pragma unroll
                 for (int m = 0; m < kMaxLevels; ++m) {
                     if (m <= tz) {
