@@ -294,7 +294,9 @@ int hrms_run_1d(hrms_handle h, const hrms_run1d_args* a, void* hip_stream);
 int hrms_run_1d_noalloc(hrms_handle h, const hrms_run1d_args* a, void* hip_stream);
 
 /* Picks the fastest compiled launch shape (threads per workgroup, outputs per
- * thread, LDS chunk or 0 for the gathered form, and the lowest top level of the
+ * thread, LDS chunk or 0 for the gathered form -- for eq. (1), 0 for loads
+ * straight from global memory and 1 for the form that stages each 512-output
+ * run's harmonic spans in LDS -- and the lowest top level of the
  * bands handed to a second launch, 0 for none: eq. (2) runs them in the window
  * form, eq. (3)-(4) in the LDS form) for batches
  * like `a` -- same variant, storage type, largest
